@@ -1,0 +1,765 @@
+// mscg_engine.hip -- host engine and C ABI of the recursive multi-scale PCG.
+//
+// The finest levels run grid-wide kernels driven from the host, one small
+// device-to-host read per CG iteration for the convergence decision.  From
+// the first level whose cell count is at most kSmallN downwards, the whole
+// inner PCG (with its own recursion and the coarsest solve) runs inside one
+// workgroup launch, so those many short iterations never leave the device.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mscg.h"
+#include "mscg_kernels.h"
+
+using namespace mscg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(MSCG_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kSmallNDefault = 4096;
+
+int small_n() {
+  static int v = [] {
+    const char* e = getenv("MSCG_SMALL_N");
+    return e ? atoi(e) : kSmallNDefault;
+  }();
+  return v;
+}
+
+struct LevelPlan {
+  int n3[3];
+  int n;
+};
+
+struct Plan {
+  int nlev;
+  LevelPlan lv[MSCG_MAX_LEVELS];
+  size_t bytes;
+};
+
+// Level hierarchy (Section 3: factor `scale` per axis, exact divisibility,
+// coarsen while every side / scale >= min_coarse_side).
+int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
+  if (!g) return fail(MSCG_E_ARG, "grid is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(MSCG_E_ARG, "dim must be 2 or 3 (got %d)", g->dim);
+  int d[3] = {g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1};
+  for (int a = 0; a < g->dim; ++a)
+    if (d[a] < 1) return fail(MSCG_E_ARG, "n[%d] = %d must be >= 1", a, d[a]);
+  const long long N = (long long)d[0] * d[1] * d[2];
+  if (N > (1LL << 30)) return fail(MSCG_E_ARG, "grid too large (%lld cells)", N);
+  for (int f = 0; f < 6; ++f)
+    if (g->bc_type[f] != MSCG_NEUMANN && g->bc_type[f] != MSCG_DIRICHLET)
+      return fail(MSCG_E_ARG, "bc_type[%d] must be MSCG_NEUMANN or MSCG_DIRICHLET", f);
+  if (o->scale < 2) return fail(MSCG_E_ARG, "scale must be >= 2");
+  if (o->smooth_steps < 1) return fail(MSCG_E_ARG, "smooth_steps must be >= 1");
+  if (!(o->level_factor > 0.0)) return fail(MSCG_E_ARG, "level_factor must be > 0");
+  if (o->interp != MSCG_INTERP_LINEAR && o->interp != MSCG_INTERP_CONSTANT) return fail(MSCG_E_ARG, "bad interp");
+  if (o->precision != MSCG_FP64 && o->precision != MSCG_MIXED) return fail(MSCG_E_ARG, "bad precision");
+  if (o->max_outer_iters < 1 || o->max_inner_iters < 1) return fail(MSCG_E_ARG, "iteration caps must be >= 1");
+  int maxl = o->max_levels < 1 ? 1 : (o->max_levels > MSCG_MAX_LEVELS ? MSCG_MAX_LEVELS : o->max_levels);
+  int nl = 0;
+  for (;;) {
+    LevelPlan& L = P->lv[nl];
+    L.n3[0] = d[0]; L.n3[1] = d[1]; L.n3[2] = d[2];
+    L.n = d[0] * d[1] * d[2];
+    ++nl;
+    if (nl >= maxl) break;
+    bool ok = true;
+    for (int a = 0; a < g->dim; ++a)
+      if (d[a] % o->scale != 0 || d[a] / o->scale < o->min_coarse_side) ok = false;
+    if (!ok) break;
+    for (int a = 0; a < g->dim; ++a) d[a] /= o->scale;
+  }
+  P->nlev = nl;
+  if (P->lv[nl - 1].n > MSCG_MAX_COARSE)
+    return fail(MSCG_E_ARG, "coarsest level has %d cells > %d: grid sides must allow coarsening by %d", P->lv[nl - 1].n,
+                MSCG_MAX_COARSE, o->scale);
+  // bytes
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
+  const bool mixed = o->precision == MSCG_MIXED;
+  for (int l = 0; l < nl; ++l) {
+    const LevelPlan& L = P->lv[l];
+    const size_t fx = (size_t)(L.n3[0] + 1) * L.n3[1] * L.n3[2], fy = (size_t)L.n3[0] * (L.n3[1] + 1) * L.n3[2];
+    const size_t fz = g->dim == 3 ? (size_t)L.n3[0] * L.n3[1] * (L.n3[2] + 1) : 0;
+    add(fx * 8); add(fy * 8); if (fz) add(fz * 8);
+    if (mixed) { add(fx * 4); add(fy * 4); if (fz) add(fz * 4); }
+    const bool fp64_vec = !mixed || l == 0;
+    for (int v = 0; v < 5; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
+    if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, smoother iterate
+    add(sizeof(Scal));
+  }
+  add((size_t)P->lv[0].n * 8);  // b
+  const size_t nc = (size_t)P->lv[nl - 1].n;
+  add(nc * nc * 8); add(nc * nc * 8); add(nc * nc * 8);  // A, Y, A^-1
+  add((size_t)kMaxPartials * 8);
+  add(64);                                              // flags
+  add(2 * MSCG_MAX_LEVELS * sizeof(long long));         // small-kernel counters
+  P->bytes = b;
+  return MSCG_OK;
+}
+
+struct LevelH {
+  int nx, ny, nz, n;
+  double hx, hy, hz;
+  int sx, sy, sz;
+  double *tx, *ty, *tz;
+  float *tx32, *ty32, *tz32;
+  double *x, *r, *z, *p, *q;  // FP64 vectors (FP64 mode, or level 0)
+  float *x32, *r32, *z32, *p32, *q32;  // FP32 vectors (mixed inner levels; level 0: r32 = scaled r, z32 = iterate)
+  Scal* sc;
+};
+
+}  // namespace
+
+struct mscg_problem {
+  mscg_grid g;
+  mscg_options o;
+  hipStream_t stream;
+  int device;
+  int nlev, ks;
+  LevelH lev[MSCG_MAX_LEVELS];
+  double *Atmp, *Ytmp, *Ainv;
+  int ncoarse;
+  double* part;
+  double* b;
+  int* dflags;        // [0] coarse factor status, [1] bad K, [2] small-kernel status
+  long long* dcount;  // [0..7] small iters, [8..15] small calls
+  Scal* hsc;          // pinned mirror of one Scal
+  int* hflags;        // pinned
+  long long* hcount;  // pinned
+  char* ws;
+  size_t ws_bytes;
+  bool owns_ws;
+  bool ready;
+  // per-solve state
+  double eps2;
+  double tol_scale;   // mixed: 1 / |r|^2 of the current outer iteration
+  long long iters[MSCG_MAX_LEVELS], calls[MSCG_MAX_LEVELS];
+  int status;
+};
+
+namespace {
+
+bool mixed(const mscg_problem* P) { return P->o.precision == MSCG_MIXED; }
+
+Lv<double> lv64(const mscg_problem* P, int k) {
+  const LevelH& L = P->lev[k];
+  return Lv<double>{L.nx, L.ny, L.nz, L.n, L.tx, L.ty, P->g.dim == 3 ? L.tz : nullptr};
+}
+Lv<float> lv32(const mscg_problem* P, int k) {
+  const LevelH& L = P->lev[k];
+  return Lv<float>{L.nx, L.ny, L.nz, L.n, L.tx32, L.ty32, P->g.dim == 3 ? L.tz32 : nullptr};
+}
+Xfer xfer(const mscg_problem* P, int k) {
+  const LevelH& F = P->lev[k];
+  const LevelH& C = P->lev[k + 1];
+  return Xfer{F.sx, F.sy, F.sz, C.nx, C.ny, C.nz, P->o.interp};
+}
+
+double level_tol(const mscg_problem* P, int k) {
+  return (double)P->lev[k].n * std::pow(P->o.level_factor, k) * P->eps2;
+}
+
+int read_scal(mscg_problem* P, int k) {
+  HIP_TRY(hipMemcpyAsync(P->hsc, P->lev[k].sc, sizeof(Scal), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int set_tol(mscg_problem* P, int k, double tol) {
+  // the tolerance lives in device scalars; a one-element fill keeps it stream ordered
+  HIP_TRY(launch_fill<double>(&P->lev[k].sc->tol, 1, tol, P->stream));
+  return MSCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-driven recursion for the large levels.  T is the storage type of the
+// level's preconditioner vectors (FP64, or FP32 in mixed mode).
+// ---------------------------------------------------------------------------
+
+int pcg_host(mscg_problem* P, int k);
+
+// Coarse part of the preconditioner on level k: y_{k+1} = A_{k+1}^-1 g.
+template <typename R>
+int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* const* zs, R* const* ps, R* const* qs) {
+  const int kc = k + 1;
+  if (kc == P->nlev - 1) {
+    HIP_TRY(launch_coarse_solve<R>(P->Ainv, rs[kc], xs[kc], P->ncoarse, P->stream));
+    P->calls[kc]++;
+    return MSCG_OK;
+  }
+  if (kc >= P->ks) {
+    SmallDesc<R> d{};
+    for (int l = 0; l < P->nlev; ++l) {
+      if (l + 1 < P->nlev) d.X[l] = xfer(P, l);
+      d.x[l] = xs[l]; d.r[l] = rs[l]; d.z[l] = zs[l]; d.p[l] = ps[l]; d.q[l] = qs[l];
+      d.tol[l] = level_tol(P, l) * P->tol_scale;
+    }
+    if constexpr (std::is_same<R, float>::value) {
+      for (int l = 0; l < P->nlev; ++l) d.L[l] = lv32(P, l);
+    } else {
+      for (int l = 0; l < P->nlev; ++l) d.L[l] = lv64(P, l);
+    }
+    d.ks = kc;
+    d.nlev = P->nlev;
+    d.m = P->o.smooth_steps;
+    d.max_inner = P->o.max_inner_iters;
+    d.rel_floor2 = mixed(P) ? P->o.inner_rel_floor * P->o.inner_rel_floor : 0.0;
+    d.Ainv = P->Ainv;
+    d.ncoarse = P->ncoarse;
+    d.iters = P->dcount;
+    d.calls = P->dcount + MSCG_MAX_LEVELS;
+    d.status = P->dflags + 2;
+    HIP_TRY(launch_small_pcg<R>(d, P->stream));
+    return MSCG_OK;
+  }
+  return pcg_host(P, kc);
+}
+
+// z_k = M_k^-1 r_k (eq. 2.10 as a two-grid cycle).  Vectors of type R.
+template <typename R>
+int precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* const* xs, R* const* rs, R* const* zs,
+                 R* const* ps, R* const* qs) {
+  const int m = P->o.smooth_steps;
+  for (int h = 0; h <= 2 * m; ++h) HIP_TRY(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream));
+  HIP_TRY(launch_restrict<R>(L, xfer(P, k), r, z, rs[k + 1], P->stream));
+  int rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
+  if (rc) return rc;
+  HIP_TRY(launch_prolong<R>(L, xfer(P, k), xs[k + 1], z, P->stream));
+  for (int h = 0; h <= 2 * m; ++h) HIP_TRY(launch_gs_half<R>(L, r, z, h & 1, 0, P->stream));
+  return MSCG_OK;
+}
+
+template <typename R>
+void vec_tables(mscg_problem* P, R** xs, R** rs, R** zs, R** ps, R** qs) {
+  for (int l = 0; l < P->nlev; ++l) {
+    LevelH& L = P->lev[l];
+    if constexpr (std::is_same<R, double>::value) {
+      xs[l] = L.x; rs[l] = L.r; zs[l] = L.z; ps[l] = L.p; qs[l] = L.q;
+    } else {
+      xs[l] = L.x32; rs[l] = L.r32; zs[l] = L.z32; ps[l] = L.p32; qs[l] = L.q32;
+    }
+  }
+}
+
+// Applies the level-k preconditioner to the level's residual into z_k.
+int apply_prec(mscg_problem* P, int k) {
+  if (!mixed(P)) {
+    double *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
+    vec_tables<double>(P, xs, rs, zs, ps, qs);
+    return precond_host<double>(P, k, lv64(P, k), P->lev[k].r, P->lev[k].z, xs, rs, zs, ps, qs);
+  }
+  float *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
+  vec_tables<float>(P, xs, rs, zs, ps, qs);
+  if (k == 0) {
+    // FP64 residual -> unit-norm FP32, precondition in FP32, scale back (Section 2.3:
+    // the inner solves only need the overall accuracy; the outer CG recovers FP64)
+    LevelH& L0 = P->lev[0];
+    HIP_TRY(launch_scale_to_f32(L0.r, L0.r32, L0.n, L0.sc, P->stream));
+    int rc = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, xs, rs, zs, ps, qs);
+    if (rc) return rc;
+    HIP_TRY(launch_scale_to_f64(L0.z32, L0.z, L0.n, L0.sc, P->stream));
+    return MSCG_OK;
+  }
+  return precond_host<float>(P, k, lv32(P, k), P->lev[k].r32, P->lev[k].z32, xs, rs, zs, ps, qs);
+}
+
+// One level's CG loop (Templates Figure 2.5) on vectors of type R; the residual
+// is in r_k and the entry check has been done by the caller (sc->converged).
+template <typename R>
+int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* q, int max_iter) {
+  LevelH& H = P->lev[k];
+  const int nb = reduce_blocks(L.n);
+  for (int it = 0; it < max_iter; ++it) {
+    int rc = apply_prec(P, k);
+    if (rc) return rc;
+    HIP_TRY(launch_dot<R>(r, z, L.n, P->part, nb, P->stream));
+    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpRho, P->stream));
+    HIP_TRY(launch_update_p<R>(z, p, L.n, H.sc, P->stream));
+    HIP_TRY(launch_spmv<R>(L, p, q, P->part, nb, P->stream));
+    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpPq, P->stream));
+    HIP_TRY(launch_cg_update<R>(x, r, p, q, L.n, H.sc, P->part, nb, P->stream));
+    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpRr, P->stream));
+    P->iters[k]++;
+    rc = read_scal(P, k);
+    if (rc) return rc;
+    if (P->hsc->status) { P->status = MSCG_E_BREAKDOWN; return MSCG_OK; }
+    if (P->hsc->converged) break;
+    if (k == 0 && mixed(P)) P->tol_scale = P->hsc->rr > 0.0 ? 1.0 / P->hsc->rr : 1.0;
+  }
+  return MSCG_OK;
+}
+
+// Inner PCG on a large level k >= 1: rhs already in r_k, x_k = 0.
+int pcg_host(mscg_problem* P, int k) {
+  LevelH& H = P->lev[k];
+  const int nb = reduce_blocks(H.n);
+  P->calls[k]++;
+  int rc = set_tol(P, k, level_tol(P, k) * P->tol_scale);
+  if (rc) return rc;
+  if (!mixed(P)) {
+    HIP_TRY(launch_fill<double>(H.x, H.n, 0.0, P->stream));
+    HIP_TRY(launch_dot<double>(H.r, H.r, H.n, P->part, nb, P->stream));
+  } else {
+    HIP_TRY(launch_fill<float>(H.x32, H.n, 0.0f, P->stream));
+    HIP_TRY(launch_dot<float>(H.r32, H.r32, H.n, P->part, nb, P->stream));
+  }
+  HIP_TRY(launch_finish(P->part, nb, H.sc, kOpEntry, P->stream));
+  rc = read_scal(P, k);
+  if (rc) return rc;
+  if (mixed(P) && P->o.inner_rel_floor > 0.0) {
+    const double floor2 = P->o.inner_rel_floor * P->o.inner_rel_floor * P->hsc->rr;
+    if (floor2 > level_tol(P, k) * P->tol_scale) {
+      rc = set_tol(P, k, floor2);
+      if (rc) return rc;
+      if (P->hsc->rr < floor2) return MSCG_OK;
+    }
+  }
+  if (P->hsc->converged) return MSCG_OK;
+  if (!mixed(P)) return cg_loop<double>(P, k, lv64(P, k), H.x, H.r, H.z, H.p, H.q, P->o.max_inner_iters);
+  return cg_loop<float>(P, k, lv32(P, k), H.x32, H.r32, H.z32, H.p32, H.q32, P->o.max_inner_iters);
+}
+
+int carve(mscg_problem* P, const Plan& plan) {
+  char* base = P->ws;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const bool mx = mixed(P);
+  const int dim = P->g.dim;
+  for (int l = 0; l < plan.nlev; ++l) {
+    LevelH& L = P->lev[l];
+    const LevelPlan& lp = plan.lv[l];
+    L.nx = lp.n3[0]; L.ny = lp.n3[1]; L.nz = lp.n3[2]; L.n = lp.n;
+    const size_t fx = (size_t)(L.nx + 1) * L.ny * L.nz, fy = (size_t)L.nx * (L.ny + 1) * L.nz;
+    const size_t fz = dim == 3 ? (size_t)L.nx * L.ny * (L.nz + 1) : 0;
+    L.tx = (double*)take(fx * 8); L.ty = (double*)take(fy * 8); L.tz = fz ? (double*)take(fz * 8) : nullptr;
+    L.tx32 = L.ty32 = L.tz32 = nullptr;
+    if (mx) { L.tx32 = (float*)take(fx * 4); L.ty32 = (float*)take(fy * 4); L.tz32 = fz ? (float*)take(fz * 4) : nullptr; }
+    L.x = L.r = L.z = L.p = L.q = nullptr;
+    L.x32 = L.r32 = L.z32 = L.p32 = L.q32 = nullptr;
+    if (!mx || l == 0) {
+      L.x = (double*)take((size_t)L.n * 8); L.r = (double*)take((size_t)L.n * 8); L.z = (double*)take((size_t)L.n * 8);
+      L.p = (double*)take((size_t)L.n * 8); L.q = (double*)take((size_t)L.n * 8);
+    } else {
+      L.x32 = (float*)take((size_t)L.n * 4); L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4);
+      L.p32 = (float*)take((size_t)L.n * 4); L.q32 = (float*)take((size_t)L.n * 4);
+    }
+    if (mx && l == 0) { L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4); }
+    L.sc = (Scal*)take(sizeof(Scal));
+  }
+  P->b = (double*)take((size_t)plan.lv[0].n * 8);
+  const size_t nc = (size_t)plan.lv[plan.nlev - 1].n;
+  P->Atmp = (double*)take(nc * nc * 8);
+  P->Ytmp = (double*)take(nc * nc * 8);
+  P->Ainv = (double*)take(nc * nc * 8);
+  P->ncoarse = (int)nc;
+  P->part = (double*)take((size_t)kMaxPartials * 8);
+  P->dflags = (int*)take(64);
+  P->dcount = (long long*)take(2 * MSCG_MAX_LEVELS * sizeof(long long));
+  if (off > P->ws_bytes) return fail(MSCG_E_NOMEM, "workspace carving overflow");
+  return MSCG_OK;
+}
+
+int validate_problem(const mscg_problem* P) {
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  return MSCG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void mscg_default_options(mscg_options* o) {
+  if (!o) return;
+  o->precision = MSCG_FP64;
+  o->scale = 4;
+  o->smooth_steps = 4;
+  o->level_factor = 0.1;
+  o->min_coarse_side = 8;
+  o->max_levels = MSCG_MAX_LEVELS;
+  o->max_outer_iters = 200;
+  o->max_inner_iters = 200;
+  o->interp = MSCG_INTERP_LINEAR;
+  o->flexible = 0;
+  o->inner_rel_floor = 1e-6;
+}
+
+const char* mscg_last_error(void) { return g_err.c_str(); }
+
+static mscg_options resolve_opts(const mscg_options* opt) {
+  mscg_options o;
+  mscg_default_options(&o);
+  if (opt) {
+    o = *opt;
+    if (o.smooth_steps <= 0) o.smooth_steps = o.scale;
+  }
+  return o;
+}
+
+size_t mscg_footprint_bytes(const mscg_grid* grid, const mscg_options* opt) {
+  g_err.clear();
+  mscg_options o = resolve_opts(opt);
+  Plan plan;
+  if (make_plan(grid, &o, &plan) != MSCG_OK) return 0;
+  return plan.bytes;
+}
+
+int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* workspace, size_t ws_bytes,
+                        void* hip_stream, mscg_problem** out) {
+  g_err.clear();
+  if (!out) return fail(MSCG_E_ARG, "out is NULL");
+  *out = nullptr;
+  mscg_options o = resolve_opts(opt);
+  Plan plan;
+  int rc = make_plan(grid, &o, &plan);
+  if (rc) return rc;
+  if (workspace && ws_bytes < plan.bytes)
+    return fail(MSCG_E_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, plan.bytes);
+  if (workspace && ((uintptr_t)workspace & 255)) return fail(MSCG_E_ARG, "workspace must be 256-byte aligned");
+  mscg_problem* P = new (std::nothrow) mscg_problem();
+  if (!P) return fail(MSCG_E_NOMEM, "host allocation failed");
+  P->g = *grid;
+  if (P->g.dim == 2) P->g.n[2] = 1;
+  for (int a = 0; a < 3; ++a)
+    if (!(P->g.length[a] > 0.0)) P->g.length[a] = 1.0;
+  P->o = o;
+  P->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&P->device) != hipSuccess) { delete P; return fail(MSCG_E_DEVICE, "hipGetDevice failed"); }
+  P->ws_bytes = plan.bytes;
+  if (workspace) {
+    P->ws = (char*)workspace;
+    P->owns_ws = false;
+  } else {
+    if (hipMalloc(&P->ws, plan.bytes) != hipSuccess) { delete P; return fail(MSCG_E_NOMEM, "hipMalloc of %zu bytes failed", plan.bytes); }
+    P->owns_ws = true;
+  }
+  if (hipHostMalloc(&P->hsc, sizeof(Scal)) != hipSuccess || hipHostMalloc(&P->hflags, 64) != hipSuccess ||
+      hipHostMalloc(&P->hcount, 2 * MSCG_MAX_LEVELS * sizeof(long long)) != hipSuccess) {
+    if (P->owns_ws) (void)hipFree(P->ws);
+    delete P;
+    return fail(MSCG_E_NOMEM, "pinned host allocation failed");
+  }
+  P->nlev = plan.nlev;
+  rc = carve(P, plan);
+  if (rc) { mscg_destroy_problem(P); return rc; }
+  const int sn = small_n();
+  P->ks = P->nlev;  // no small level
+  for (int l = 1; l < P->nlev - 1; ++l)
+    if (P->lev[l].n <= sn) { P->ks = l; break; }
+  for (int l = 0; l < P->nlev; ++l) {
+    LevelH& L = P->lev[l];
+    L.hx = P->g.length[0] / L.nx;
+    L.hy = P->g.length[1] / L.ny;
+    L.hz = P->g.dim == 3 ? P->g.length[2] / L.nz : 1.0;
+    if (l + 1 < P->nlev) {
+      L.sx = L.nx / plan.lv[l + 1].n3[0];
+      L.sy = L.ny / plan.lv[l + 1].n3[1];
+      L.sz = L.nz / plan.lv[l + 1].n3[2];
+    } else {
+      L.sx = L.sy = L.sz = 1;
+    }
+  }
+  P->ready = false;
+  *out = P;
+  return MSCG_OK;
+}
+
+int mscg_destroy_problem(mscg_problem* P) {
+  if (!P) return MSCG_OK;
+  if (P->owns_ws && P->ws) (void)hipFree(P->ws);
+  if (P->hsc) (void)hipHostFree(P->hsc);
+  if (P->hflags) (void)hipHostFree(P->hflags);
+  if (P->hcount) (void)hipHostFree(P->hcount);
+  delete P;
+  return MSCG_OK;
+}
+
+int mscg_set_permeability(mscg_problem* P, const double* kx, const double* ky, const double* kz) {
+  g_err.clear();
+  int rc = validate_problem(P);
+  if (rc) return rc;
+  if (!kx) return fail(MSCG_E_ARG, "kx is NULL");
+  if (!ky) ky = kx;
+  if (P->g.dim == 3 && !kz) kz = kx;
+  LevelH& L0 = P->lev[0];
+  const long long N = L0.n;
+  // validate K > 0 and finite
+  HIP_TRY(launch_fill<int>(P->dflags, 16, 0, P->stream));
+  HIP_TRY(launch_check_positive(kx, N, P->dflags + 1, P->stream));
+  HIP_TRY(launch_check_positive(ky, N, P->dflags + 1, P->stream));
+  if (P->g.dim == 3) HIP_TRY(launch_check_positive(kz, N, P->dflags + 1, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (P->hflags[1]) return fail(MSCG_E_ARG, "permeability must be finite and > 0 everywhere");
+  // face transmissibilities of level 0
+  FaceTArgs fa{};
+  fa.dim = P->g.dim; fa.nx = L0.nx; fa.ny = L0.ny; fa.nz = L0.nz;
+  fa.ax = L0.hy * L0.hz / L0.hx;
+  fa.ay = L0.hx * L0.hz / L0.hy;
+  fa.az = L0.hx * L0.hy / L0.hz;
+  fa.kx = kx; fa.ky = ky; fa.kz = kz;
+  for (int f = 0; f < 6; ++f) fa.bc_type[f] = P->g.bc_type[f];
+  if (P->g.dim == 2) { fa.bc_type[4] = fa.bc_type[5] = 0; }
+  fa.tx = L0.tx; fa.ty = L0.ty; fa.tz = L0.tz;
+  HIP_TRY(launch_face_T(fa, P->stream));
+  // coarse graining level by level
+  for (int l = 1; l < P->nlev; ++l) {
+    LevelH& F = P->lev[l - 1];
+    LevelH& C = P->lev[l];
+    const double* fsrc[3] = {F.tx, F.ty, F.tz};
+    double* cdst[3] = {C.tx, C.ty, C.tz};
+    for (int ax = 0; ax < P->g.dim; ++ax) {
+      CoarsenArgs ca{};
+      ca.axis = ax;
+      ca.fd[0] = F.nx; ca.fd[1] = F.ny; ca.fd[2] = F.nz;
+      ca.cd[0] = C.nx; ca.cd[1] = C.ny; ca.cd[2] = C.nz;
+      ca.s[0] = F.sx; ca.s[1] = F.sy; ca.s[2] = F.sz;
+      ca.f = fsrc[ax];
+      ca.c = cdst[ax];
+      HIP_TRY(launch_coarsen(ca, P->stream));
+    }
+  }
+  if (mixed(P)) {
+    for (int l = 0; l < P->nlev; ++l) {
+      LevelH& L = P->lev[l];
+      HIP_TRY(launch_to_f32(L.tx, L.tx32, (long long)(L.nx + 1) * L.ny * L.nz, P->stream));
+      HIP_TRY(launch_to_f32(L.ty, L.ty32, (long long)L.nx * (L.ny + 1) * L.nz, P->stream));
+      if (P->g.dim == 3) HIP_TRY(launch_to_f32(L.tz, L.tz32, (long long)L.nx * L.ny * (L.nz + 1), P->stream));
+    }
+  }
+  // coarsest factorisation
+  HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Ytmp, P->Ainv, P->dflags, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (P->hflags[0]) {
+    P->ready = false;
+    return fail(MSCG_E_SINGULAR, "coarsest operator is not positive definite (no Dirichlet boundary?)");
+  }
+  P->ready = true;
+  return MSCG_OK;
+}
+
+static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_tol, int use_x0, mscg_stats* st) {
+  auto t0 = std::chrono::steady_clock::now();
+  LevelH& L0 = P->lev[0];
+  const int N = L0.n;
+  const int nb = reduce_blocks(N);
+  for (int l = 0; l < MSCG_MAX_LEVELS; ++l) { P->iters[l] = 0; P->calls[l] = 0; }
+  P->status = MSCG_OK;
+  P->tol_scale = 1.0;
+  HIP_TRY(launch_fill<long long>(P->dcount, 2 * MSCG_MAX_LEVELS, 0, P->stream));
+  HIP_TRY(launch_fill<int>(P->dflags + 2, 1, 0, P->stream));
+  // right-hand side and tolerance
+  RhsArgs ra{};
+  ra.dim = P->g.dim; ra.nx = L0.nx; ra.ny = L0.ny; ra.nz = L0.nz; ra.n = N;
+  ra.vol = L0.hx * L0.hy * L0.hz;
+  ra.f = f; ra.tx = L0.tx; ra.ty = L0.ty; ra.tz = L0.tz;
+  for (int q = 0; q < 6; ++q) { ra.bc_type[q] = P->g.bc_type[q]; ra.bc_value[q] = P->g.bc_value[q]; }
+  if (P->g.dim == 2) { ra.bc_type[4] = ra.bc_type[5] = 0; }
+  ra.b = P->b;
+  HIP_TRY(launch_rhs(ra, P->stream));
+  HIP_TRY(launch_dot<double>(P->b, P->b, N, P->part, nb, P->stream));
+  HIP_TRY(launch_finish(P->part, nb, L0.sc, kOpBB, P->stream));
+  int rc = read_scal(P, 0);
+  if (rc) return rc;
+  const double bb = P->hsc->bb;
+  P->eps2 = rel_tol * rel_tol * bb / N;
+  // initial guess
+  bool only_x = P->g.bc_type[0] == MSCG_DIRICHLET && P->g.bc_type[1] == MSCG_DIRICHLET;
+  for (int q = 2; q < 2 * P->g.dim; ++q) if (P->g.bc_type[q] == MSCG_DIRICHLET) only_x = false;
+  if (!use_x0)
+    HIP_TRY(launch_init_x(p, N, L0.nx, L0.hx, P->g.length[0], P->g.bc_value[0], P->g.bc_value[1], only_x ? 1 : 0,
+                          P->stream));
+  int outer = 0;
+  if (P->nlev == 1) {
+    HIP_TRY(launch_coarse_solve<double>(P->Ainv, P->b, p, N, P->stream));
+    P->calls[0]++;
+  } else {
+    rc = set_tol(P, 0, level_tol(P, 0));
+    if (rc) return rc;
+    HIP_TRY(launch_residual<double>(lv64(P, 0), P->b, p, L0.r, P->part, nb, P->stream));
+    HIP_TRY(launch_finish(P->part, nb, L0.sc, kOpEntry, P->stream));
+    rc = read_scal(P, 0);
+    if (rc) return rc;
+    P->calls[0]++;
+    if (!P->hsc->converged) {
+      if (mixed(P)) P->tol_scale = P->hsc->rr > 0.0 ? 1.0 / P->hsc->rr : 1.0;
+      rc = cg_loop<double>(P, 0, lv64(P, 0), p, L0.r, L0.z, L0.p, L0.q, P->o.max_outer_iters);
+      if (rc) return rc;
+    }
+    outer = (int)P->iters[0];
+  }
+  // true residual in FP64
+  HIP_TRY(launch_residual<double>(lv64(P, 0), P->b, p, L0.z, P->part, nb, P->stream));
+  HIP_TRY(launch_finish(P->part, nb, L0.sc, kOpBB, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->hcount, P->dcount, 2 * MSCG_MAX_LEVELS * sizeof(long long), hipMemcpyDeviceToHost,
+                         P->stream));
+  HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
+  rc = read_scal(P, 0);
+  if (rc) return rc;
+  const double rt = P->hsc->bb;
+  auto t1 = std::chrono::steady_clock::now();
+  int status = P->status;
+  if (P->hflags[2]) status = MSCG_E_BREAKDOWN;
+  const bool converged_rec = P->nlev == 1 || P->hsc->converged;
+  if (status == MSCG_OK && !converged_rec) status = MSCG_NOT_CONVERGED;
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->status = status;
+    st->outer_iters = outer;
+    st->n_levels = P->nlev;
+    for (int l = 0; l < P->nlev; ++l) {
+      st->level_n[l][0] = P->lev[l].nx; st->level_n[l][1] = P->lev[l].ny; st->level_n[l][2] = P->lev[l].nz;
+      st->level_iters[l] = P->iters[l] + P->hcount[l];
+      st->level_calls[l] = P->calls[l] + P->hcount[MSCG_MAX_LEVELS + l];
+    }
+    st->b_norm = std::sqrt(bb);
+    st->rel_residual_true = bb > 0.0 ? std::sqrt(rt / bb) : std::sqrt(rt);
+    st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  return status;
+}
+
+int mscg_solve(mscg_problem* P, const double* f, double* p, double rel_tol, int use_x0, mscg_stats* st) {
+  g_err.clear();
+  int rc = validate_problem(P);
+  if (rc) return rc;
+  if (!P->ready) return fail(MSCG_E_STATE, "mscg_set_permeability must succeed before mscg_solve");
+  if (!f || !p) return fail(MSCG_E_ARG, "f and p must be device pointers");
+  if (!(rel_tol > 0.0) || !(rel_tol < 1.0)) return fail(MSCG_E_ARG, "rel_tol must be in (0, 1)");
+  return solve_impl(P, f, p, rel_tol, use_x0, st);
+}
+
+int mscg_solve_batch(mscg_problem* const* probs, const double* const* f, double* const* p, const double* rel_tol,
+                     int count, mscg_stats* stats) {
+  g_err.clear();
+  if (count < 0 || (count > 0 && (!probs || !f || !p || !rel_tol))) return fail(MSCG_E_ARG, "bad batch arguments");
+  int worst = MSCG_OK;
+  for (int i = 0; i < count; ++i) {
+    const int rc = mscg_solve(probs[i], f[i], p[i], rel_tol[i], 0, stats ? &stats[i] : nullptr);
+    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+    else if (rc > 0 && worst == MSCG_OK) worst = rc;
+  }
+  return worst;
+}
+
+int mscg_level_info(const mscg_problem* P, int level, int dims[3]) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level %d out of range (%d levels)", level, P->nlev);
+  if (dims) { dims[0] = P->lev[level].nx; dims[1] = P->lev[level].ny; dims[2] = P->lev[level].nz; }
+  return P->nlev;
+}
+
+int mscg_get_transmissibility(const mscg_problem* P, int level, double* tx, double* ty, double* tz) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level out of range");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  const LevelH& L = P->lev[level];
+  HIP_TRY(launch_copy<double>(L.tx, tx, (long long)(L.nx + 1) * L.ny * L.nz, P->stream));
+  HIP_TRY(launch_copy<double>(L.ty, ty, (long long)L.nx * (L.ny + 1) * L.nz, P->stream));
+  if (P->g.dim == 3 && tz) HIP_TRY(launch_copy<double>(L.tz, tz, (long long)L.nx * L.ny * (L.nz + 1), P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int mscg_apply_operator(mscg_problem* P, int level, const double* x, double* y) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level out of range");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  HIP_TRY(launch_spmv<double>(lv64(P, level), x, y, nullptr, reduce_blocks(P->lev[level].n), P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int mscg_apply_smoother(mscg_problem* P, int level, const double* r, double* x, int steps) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level out of range");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  if (steps < 1) return fail(MSCG_E_ARG, "steps must be >= 1");
+  // steps forward+backward pairs (R,B | B,R) with repeated colours elided: R,B,R,...,R
+  for (int h = 0; h <= 2 * steps; ++h) HIP_TRY(launch_gs_half<double>(lv64(P, level), r, x, h & 1, 0, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int mscg_restrict_residual(mscg_problem* P, int level, const double* r, const double* x, double* g) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level + 1 >= P->nlev) return fail(MSCG_E_ARG, "level must have a coarser level");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  HIP_TRY(launch_restrict<double>(lv64(P, level), xfer(P, level), r, x, g, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int mscg_prolong_add(mscg_problem* P, int level, const double* y, double* x) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (level < 0 || level + 1 >= P->nlev) return fail(MSCG_E_ARG, "level must have a coarser level");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  HIP_TRY(launch_prolong<double>(lv64(P, level), xfer(P, level), y, x, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return MSCG_OK;
+}
+
+int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, double eps2) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  if (mixed(P)) return fail(MSCG_E_ARG, "mscg_apply_preconditioner needs an FP64 problem");
+  if (P->nlev < 2) return fail(MSCG_E_ARG, "a preconditioner needs at least two levels");
+  for (int l = 0; l < MSCG_MAX_LEVELS; ++l) { P->iters[l] = 0; P->calls[l] = 0; }
+  P->eps2 = eps2;
+  P->tol_scale = 1.0;
+  P->status = MSCG_OK;
+  LevelH& L0 = P->lev[0];
+  HIP_TRY(launch_copy<double>(r, L0.r, L0.n, P->stream));
+  HIP_TRY(launch_fill<long long>(P->dcount, 2 * MSCG_MAX_LEVELS, 0, P->stream));
+  int rc = apply_prec(P, 0);
+  if (rc) return rc;
+  HIP_TRY(launch_copy<double>(L0.z, z, L0.n, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return P->status;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// mscg_kernels.h -- launcher interface between the host engine and the gfx950
+// kernels of the recursive multi-scale PCG.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mscg_dev.h"
+
+namespace mscg {
+
+constexpr int kMaxPartials = 1024;  // blocks of a grid-wide reduction
+
+// Device-resident scalars of one level's CG (Templates Figure 2.5).
+struct Scal {
+  double bb;    // |b|^2 (finest level)
+  double rr;    // |r|^2 after the last update
+  double rho;   // r . z of the current iteration
+  double beta;  // rho / rho_previous
+  double alpha; // rho / (p . A p)
+  double tol;   // absolute criterion on |r|^2: N_k f^k eps^2
+  int it;       // iterations done in the current call
+  int converged;
+  int status;   // 0 or -4 (breakdown)
+  int pad;
+};
+
+enum { kOpBB = 0, kOpEntry = 1, kOpRho = 2, kOpPq = 3, kOpRr = 4 };
+
+struct FaceTArgs {
+  int dim, nx, ny, nz;
+  double ax, ay, az;  // area / distance per axis
+  const double *kx, *ky, *kz;
+  int bc_type[6];
+  double *tx, *ty, *tz;
+};
+
+struct CoarsenArgs {
+  int axis;
+  int fd[3], cd[3], s[3];
+  const double* f;
+  double* c;
+};
+
+struct RhsArgs {
+  int dim, nx, ny, nz, n;
+  double vol;
+  const double* f;
+  const double *tx, *ty, *tz;
+  int bc_type[6];
+  double bc_value[6];
+  double* b;
+};
+
+template <typename R>
+struct SmallDesc {
+  Lv<R> L[kMaxLevels];
+  Xfer X[kMaxLevels];
+  R *x[kMaxLevels], *r[kMaxLevels], *z[kMaxLevels], *p[kMaxLevels], *q[kMaxLevels];
+  double tol[kMaxLevels];
+  int ks, nlev, m, max_inner;
+  double rel_floor2;
+  const double* Ainv;
+  int ncoarse;
+  long long *iters, *calls;
+  int* status;
+};
+
+hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s);
+hipError_t launch_check_positive(const double* k, long long n, int* bad, hipStream_t s);
+hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s);
+hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Y, double* Ainv, int* status, hipStream_t s);
+hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s);
+hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
+hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp, hipStream_t s);
+hipError_t launch_scale_to_f32(const double* a, float* b, int n, const Scal* sc, hipStream_t s);
+hipError_t launch_scale_to_f64(const float* a, double* b, int n, const Scal* sc, hipStream_t s);
+
+template <typename R>
+hipError_t launch_spmv(const Lv<R>& L, const R* x, R* y, double* part, int nparts, hipStream_t s);
+template <typename R>
+hipError_t launch_residual(const Lv<R>& L, const R* b, const R* x, R* r, double* part, int nparts, hipStream_t s);
+template <typename R>
+hipError_t launch_dot(const R* a, const R* b, int n, double* part, int nparts, hipStream_t s);
+template <typename R>
+hipError_t launch_update_p(const R* z, R* p, int n, const Scal* sc, hipStream_t s);
+template <typename R>
+hipError_t launch_cg_update(R* x, R* r, const R* p, const R* q, int n, const Scal* sc, double* part, int nparts,
+                            hipStream_t s);
+template <typename R>
+hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s);
+template <typename R>
+hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s);
+template <typename R>
+hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s);
+template <typename R>
+hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s);
+template <typename R>
+hipError_t launch_fill(R* a, long long n, R v, hipStream_t s);
+template <typename R>
+hipError_t launch_copy(const R* a, R* b, long long n, hipStream_t s);
+template <typename R>
+hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s);
+
+// Number of blocks (= partials) of a grid-wide reduction over n cells.
+inline int reduce_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > kMaxPartials) b = kMaxPartials;
+  return (int)b;
+}
+
+}  // namespace mscg

@@ -1,0 +1,742 @@
+// mscg_kernels.hip -- gfx950 kernels of the recursive multi-scale PCG and
+// their launchers.  All work is stream ordered; nothing here synchronises.
+#include "mscg_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include "mscg_dev.h"
+
+namespace mscg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(long long n, int max_blocks = kMaxPartials) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Setup: face transmissibilities (Section 3: harmonic mean of the adjacent
+// cells times area / distance; a Dirichlet boundary face is held at the face,
+// half a cell away, so T = 2 K area / width; a Neumann face has T = 0).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+
+__global__ void k_face_T(FaceTArgs a) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long nfx = (long long)(nx + 1) * ny * nz, nfy = (long long)nx * (ny + 1) * nz;
+  const long long nfz = a.dim == 3 ? (long long)nx * ny * (nz + 1) : 0;
+  if (t < nfx) {
+    const int i = (int)(t % (nx + 1));
+    const long long row = t / (nx + 1);  // j + ny*k
+    const long long c = (long long)nx * row + i;
+    double v;
+    if (i == 0) v = a.bc_type[0] == 1 ? 2.0 * a.ax * a.kx[c] : 0.0;
+    else if (i == nx) v = a.bc_type[1] == 1 ? 2.0 * a.ax * a.kx[c - 1] : 0.0;
+    else v = a.ax * harm(a.kx[c - 1], a.kx[c]);
+    a.tx[t] = v;
+    return;
+  }
+  long long u = t - nfx;
+  if (u < nfy) {
+    const int i = (int)(u % nx);
+    const long long r2 = u / nx;
+    const int j = (int)(r2 % (ny + 1));
+    const long long k = r2 / (ny + 1);
+    const long long c = i + (long long)nx * (j + (long long)ny * k);
+    double v;
+    if (j == 0) v = a.bc_type[2] == 1 ? 2.0 * a.ay * a.ky[c] : 0.0;
+    else if (j == ny) v = a.bc_type[3] == 1 ? 2.0 * a.ay * a.ky[c - nx] : 0.0;
+    else v = a.ay * harm(a.ky[c - nx], a.ky[c]);
+    a.ty[u] = v;
+    return;
+  }
+  u -= nfy;
+  if (u < nfz) {
+    const long long plane = (long long)nx * ny;
+    const long long k = u / plane;
+    const long long cxy = u - k * plane;
+    double v;
+    if (k == 0) v = a.bc_type[4] == 1 ? 2.0 * a.az * a.kz[cxy] : 0.0;
+    else if (k == nz) v = a.bc_type[5] == 1 ? 2.0 * a.az * a.kz[cxy + plane * (nz - 1)] : 0.0;
+    else v = a.az * harm(a.kz[cxy + plane * (k - 1)], a.kz[cxy + plane * k]);
+    a.tz[u] = v;
+  }
+}
+
+// Validation of K: counts entries that are not finite or not > 0.
+__global__ void k_check_positive(const double* __restrict__ k, long long n, int* __restrict__ bad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  int b = 0;
+  for (long long c = t; c < n; c += stride) {
+    const double v = k[c];
+    if (!(v > 0.0) || !(v < INFINITY)) b = 1;
+  }
+  if (b) atomicOr(bad, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse graining (Section 3): 1/T^c = sum_i alpha_i / (sum_j T(i, j)).
+// The control volume of a face spans the two adjacent cell centres (half a
+// cell at the boundary).  Fine face i covers [i-1/2, i+1/2] (fine units,
+// clipped to [0, nf]); coarse face I covers [s(I-1/2), s(I+1/2)] clipped to
+// [0, s nc].  alpha_i = overlap / width of the fine span; j runs over the
+// fine faces inside the coarse face.  A zero parallel sum (no-flow column)
+// gives a zero coarse face.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double span_overlap(int i, int I, int s, int nf, int nc) {
+  const double a0 = i == 0 ? 0.0 : i - 0.5, a1 = i == nf ? (double)nf : i + 0.5;
+  const double b0 = I == 0 ? 0.0 : s * (I - 0.5), b1 = I == nc ? (double)s * nc : s * (I + 0.5);
+  const double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+  return hi > lo ? (hi - lo) / (a1 - a0) : 0.0;
+}
+
+__global__ void k_coarsen_axis(CoarsenArgs a) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // coarse face array dims (face axis extended by one)
+  int ce[3] = {a.cd[0], a.cd[1], a.cd[2]};
+  int fe[3] = {a.fd[0], a.fd[1], a.fd[2]};
+  ce[a.axis] += 1;
+  fe[a.axis] += 1;
+  const long long total = (long long)ce[0] * ce[1] * ce[2];
+  if (t >= total) return;
+  int C[3];
+  C[0] = (int)(t % ce[0]);
+  C[1] = (int)((t / ce[0]) % ce[1]);
+  C[2] = (int)(t / ((long long)ce[0] * ce[1]));
+  const int ax = a.axis, a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+  const int s = a.s[ax], I = C[ax];
+  int lo = s * I - s, hi = s * I + s;
+  if (lo < 0) lo = 0;
+  if (hi > a.fd[ax]) hi = a.fd[ax];
+  double inv = 0.0;
+  bool blocked = false;
+  for (int i = lo; i <= hi && !blocked; ++i) {
+    const double alpha = span_overlap(i, I, s, a.fd[ax], a.cd[ax]);
+    if (alpha == 0.0) continue;
+    double par = 0.0;
+    for (int u = 0; u < a.s[a1]; ++u)
+      for (int v = 0; v < a.s[a2]; ++v) {
+        int F[3];
+        F[ax] = i;
+        F[a1] = C[a1] * a.s[a1] + u;
+        F[a2] = C[a2] * a.s[a2] + v;
+        par += a.f[F[0] + (long long)fe[0] * (F[1] + (long long)fe[1] * F[2])];
+      }
+    if (par == 0.0) blocked = true;
+    else inv += alpha / par;
+  }
+  a.c[t] = blocked ? 0.0 : 1.0 / inv;
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long c = t; c < n; c += stride) b[c] = (float)a[c];
+}
+
+// Dense operator of the coarsest level, column c = A e_c, row-major n x n.
+__global__ void k_dense_assemble(Lv<double> L, double* __restrict__ A) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = L.n;
+  if (c >= n) return;
+  int i, j, k;
+  cell_ijk(c, L.nx, L.ny, i, j, k);
+  // row c of A: diag at c, -T at neighbours (A is symmetric)
+  for (int q = 0; q < n; ++q) A[(long long)c * n + q] = 0.0;
+  const int fx = i + (L.nx + 1) * (j + L.ny * k), fy = i + L.nx * (j + (L.ny + 1) * k);
+  double d = L.tx[fx] + L.tx[fx + 1] + L.ty[fy] + L.ty[fy + L.nx];
+  if (i > 0) A[(long long)c * n + c - 1] = -L.tx[fx];
+  if (i < L.nx - 1) A[(long long)c * n + c + 1] = -L.tx[fx + 1];
+  if (j > 0) A[(long long)c * n + c - L.nx] = -L.ty[fy];
+  if (j < L.ny - 1) A[(long long)c * n + c + L.nx] = -L.ty[fy + L.nx];
+  if (L.tz) {
+    const int plane = L.nx * L.ny, fz = i + L.nx * j + plane * k;
+    d += L.tz[fz] + L.tz[fz + plane];
+    if (k > 0) A[(long long)c * n + c - plane] = -L.tz[fz];
+    if (k < L.nz - 1) A[(long long)c * n + c + plane] = -L.tz[fz + plane];
+  }
+  A[(long long)c * n + c] = d;
+}
+
+// Coarsest factorisation (Section 2.2/2.3: the recursion ends with an exact
+// solve): right-looking Cholesky A = L L^T in place (one workgroup), then
+// Y = L^-1 one column per thread, then A^-1 = Y^T Y, stored row-major so
+// y = A^-1 g is a coalesced matrix-vector product.  status[0] = 1 if A is not
+// positive definite.
+__global__ void __launch_bounds__(1024) k_cholesky_inverse(double* __restrict__ A, double* __restrict__ Y,
+                                                           double* __restrict__ Ainv, int n, int* __restrict__ status) {
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      const double d = A[(long long)j * n + j];
+      if (!(d > 0.0)) bad = 1;
+      A[(long long)j * n + j] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double djj = A[(long long)j * n + j];
+    for (int i = j + 1 + tid; i < n; i += nt) A[(long long)i * n + j] /= djj;
+    __syncthreads();
+    // trailing update of the lower triangle: rows i > j, columns j < l <= i
+    const long long m = n - j - 1;
+    const long long cnt = m * (m + 1) / 2;
+    for (long long e = tid; e < cnt; e += nt) {
+      // e -> (ii, ll) with 0 <= ll <= ii < m, row-major over the triangle
+      long long ii = (long long)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while (ii * (ii + 1) / 2 > e) --ii;
+      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      const long long ll = e - ii * (ii + 1) / 2;
+      const long long i = j + 1 + ii, l = j + 1 + ll;
+      A[i * n + l] -= A[i * n + j] * A[l * n + j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) status[0] = 1;
+    return;
+  }
+  // Y = L^-1 (lower triangular), column c by thread c
+  for (int c = tid; c < n; c += nt) {
+    for (int i = 0; i < n; ++i) {
+      if (i < c) { Y[(long long)i * n + c] = 0.0; continue; }
+      double s = i == c ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= A[(long long)i * n + k] * Y[(long long)k * n + c];
+      Y[(long long)i * n + c] = s / A[(long long)i * n + i];
+    }
+  }
+  __syncthreads();
+  // A^-1 = Y^T Y: (i, l) = sum_{k >= max(i,l)} Y[k][i] Y[k][l]
+  const long long nn = (long long)n * n;
+  for (long long e = tid; e < nn; e += nt) {
+    const int i = (int)(e / n), l = (int)(e % n);
+    const int k0 = i > l ? i : l;
+    double s = 0.0;
+    for (int k = k0; k < n; ++k) s += Y[(long long)k * n + i] * Y[(long long)k * n + l];
+    Ainv[e] = s;
+  }
+  if (tid == 0) status[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Solve-phase kernels (grid-wide).  Reductions write one partial per block;
+// k_finish_* sums them in block order in one workgroup, so every result is
+// independent of scheduling.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot(Lv<R> L, const R* __restrict__ x, R* __restrict__ y,
+                                                      double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  const double acc = spmv_range<R, double>(L, x, y, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0 && part) part[blockIdx.x] = s;
+}
+
+// r = b - A x, partial |r|^2
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_residual(Lv<R> L, const R* __restrict__ b, const R* __restrict__ x,
+                                                      R* __restrict__ r, double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, L.nx, L.ny, i, j, k);
+    R d, o;
+    stencil_at(L, x, i, j, k, c, d, o);
+    const R v = b[c] - (d * x[c] - o);
+    r[c] = v;
+    acc += (double)v * (double)v;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_dot(const R* __restrict__ a, const R* __restrict__ b, int n,
+                                                 double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    acc += (double)a[c] * (double)b[c];
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = z (first iteration) or p = z + beta p
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_update_p(const R* __restrict__ z, R* __restrict__ p, int n,
+                                                      const Scal* __restrict__ sc) {
+  const bool first = sc->it == 0;
+  const R beta = (R)sc->beta;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    p[c] = first ? z[c] : z[c] + beta * p[c];
+}
+
+// x += alpha p, r -= alpha q, partial |r|^2
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cg_update(R* __restrict__ x, R* __restrict__ r, const R* __restrict__ p,
+                                                       const R* __restrict__ q, int n, const Scal* __restrict__ sc,
+                                                       double* __restrict__ part) {
+  __shared__ double sm[kBlock / kWave];
+  const R alpha = (R)sc->alpha;
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    x[c] += alpha * p[c];
+    const R v = r[c] - alpha * q[c];
+    r[c] = v;
+    acc += (double)v * (double)v;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_gs_half(Lv<R> L, const R* __restrict__ r, R* __restrict__ x, int colour,
+                                                     int first) {
+  gs_half_range(L, r, x, colour, first != 0, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_restrict(Lv<R> F, Xfer X, const R* __restrict__ r,
+                                                      const R* __restrict__ x, R* __restrict__ g) {
+  restrict_range(F, X, r, x, g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_prolong(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x) {
+  prolong_range(F, X, y, x, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// y = A^-1 g on the coarsest level (dense FP64 inverse; g, y in R).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restrict__ Ainv, const R* __restrict__ g,
+                                                          R* __restrict__ y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s += Ainv[(long long)j * n + i] * (double)g[j];
+  y[i] = (R)s;
+}
+
+// Scalar bookkeeping of one level's CG (Templates Figure 2.5), one workgroup.
+__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
+                                                   int op) {
+  __shared__ double sm[kBlock / kWave];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) acc += part[q];
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case kOpBB:
+      sc->bb = s;
+      break;
+    case kOpEntry:  // entry check of the level criterion
+      sc->rr = s;
+      sc->it = 0;
+      sc->converged = s < sc->tol ? 1 : 0;
+      if (!(s == s) || s == INFINITY) sc->status = -4;
+      break;
+    case kOpRho:
+      if (!(s > 0.0) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
+      sc->beta = sc->it == 0 ? 0.0 : s / sc->rho;
+      sc->rho = s;
+      break;
+    case kOpPq:
+      if (!(s > 0.0) || s == INFINITY) { sc->status = -4; sc->converged = 1; sc->alpha = 0.0; }
+      else sc->alpha = sc->rho / s;
+      break;
+    case kOpRr:
+      sc->rr = s;
+      sc->it += 1;
+      if (s < sc->tol) sc->converged = 1;
+      if (!(s == s) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
+      break;
+  }
+}
+
+// b = f |V| + sum over Dirichlet boundary faces of T_b p_D (level 0).
+__global__ void k_rhs(RhsArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  int i, j, k;
+  cell_ijk(c, a.nx, a.ny, i, j, k);
+  double v = a.f[c] * a.vol;
+  if (i == 0 && a.bc_type[0] == 1) v += a.tx[(a.nx + 1) * (j + a.ny * k)] * a.bc_value[0];
+  if (i == a.nx - 1 && a.bc_type[1] == 1) v += a.tx[a.nx + (a.nx + 1) * (j + a.ny * k)] * a.bc_value[1];
+  if (j == 0 && a.bc_type[2] == 1) v += a.ty[i + a.nx * (a.ny + 1) * k] * a.bc_value[2];
+  if (j == a.ny - 1 && a.bc_type[3] == 1) v += a.ty[i + a.nx * (a.ny + (a.ny + 1) * k)] * a.bc_value[3];
+  if (a.dim == 3) {
+    const int plane = a.nx * a.ny;
+    if (k == 0 && a.bc_type[4] == 1) v += a.tz[i + a.nx * j] * a.bc_value[4];
+    if (k == a.nz - 1 && a.bc_type[5] == 1) v += a.tz[i + a.nx * j + plane * a.nz] * a.bc_value[5];
+  }
+  a.b[c] = v;
+}
+
+// Initial guess: linear ramp between the x-face Dirichlet values (lifting by
+// a smooth field matching the boundary data, Section 3) or zero.
+__global__ void k_init_x(double* __restrict__ x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int i = c % nx;
+  x[c] = ramp ? p0 + (p1 - p0) * ((i + 0.5) * hx) / Lx : 0.0;
+}
+
+template <typename R>
+__global__ void k_fill(R* __restrict__ a, long long n, R v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long c = t; c < n; c += stride) a[c] = v;
+}
+
+template <typename R>
+__global__ void k_copy(const R* __restrict__ a, R* __restrict__ b, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long c = t; c < n; c += stride) b[c] = a[c];
+}
+
+// Mixed precision seam: out32 = in64 * scale and out64 = in32 * scale.
+__global__ void k_scale_to_f32(const double* __restrict__ a, float* __restrict__ b, int n, const Scal* __restrict__ sc) {
+  const double s = sc->rr > 0.0 ? 1.0 / sqrt(sc->rr) : 1.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) b[c] = (float)(a[c] * s);
+}
+__global__ void k_scale_to_f64(const float* __restrict__ a, double* __restrict__ b, int n, const Scal* __restrict__ sc) {
+  const double s = sc->rr > 0.0 ? sqrt(sc->rr) : 1.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) b[c] = (double)a[c] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Small levels: the inner PCG of level ks and every level below it run in
+// ONE workgroup, with the recursion unrolled into a loop over an explicit
+// level stack.  No host round trip per iteration: the control flow that the
+// paper's level tree describes (dynamic transitions, Section 4) happens on
+// the device.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct SmallLevel {
+  Lv<R> L;
+  Xfer X;                 // to level + 1
+  R *x, *r, *z, *p, *q;   // q may alias nothing
+  double tol;             // absolute criterion on |r|^2
+};
+
+template <typename R>
+struct SmallArgs {
+  SmallLevel<R> lv[kMaxLevels];
+  int ks, nlev;           // first small level, total levels
+  int m, max_inner;
+  double rel_floor2;      // (floor)^2 relative to |rhs|^2, 0 = off
+  const double* Ainv;
+  int ncoarse;
+  long long* iters;       // per level, accumulated (device)
+  long long* calls;
+  int* status;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
+  __shared__ double sm[1024 / kWave];
+  __shared__ double sh_rho[kMaxLevels], sh_rr[kMaxLevels], sh_tol[kMaxLevels];
+  __shared__ int sh_it[kMaxLevels];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int L = a.nlev - 1;  // coarsest index
+  long long my_iters[kMaxLevels], my_calls[kMaxLevels];
+  for (int l = 0; l < kMaxLevels; ++l) { my_iters[l] = 0; my_calls[l] = 0; }
+  int status = 0;
+
+  // start the PCG of level k: x = 0, r already holds the rhs.  Returns true if
+  // the entry check is already satisfied.
+  auto start = [&](int k) -> bool {
+    SmallLevel<R>& S = a.lv[k];
+    for (int c = tid; c < S.L.n; c += nt) S.x[c] = R(0);
+    double acc = 0.0;
+    for (int c = tid; c < S.L.n; c += nt) acc += (double)S.r[c] * (double)S.r[c];
+    const double rr = block_sum(acc, sm);
+    double tol = S.tol;
+    if (a.rel_floor2 > 0.0 && a.rel_floor2 * rr > tol) tol = a.rel_floor2 * rr;
+    if (tid == 0) { sh_rr[k] = rr; sh_tol[k] = tol; sh_it[k] = 0; }
+    my_calls[k] += 1;
+    __syncthreads();
+    return rr < tol;
+  };
+  // pre-smoothing of level k from x = 0 (m SGS steps = R,B,R,...,R: 2m+1 half
+  // sweeps, repeated colours being idempotent) and g_{k+1} = E^T (r - A z).
+  auto pre = [&](int k) {
+    SmallLevel<R>& S = a.lv[k];
+    for (int h = 0; h <= 2 * a.m; ++h) {
+      gs_half_range(S.L, S.r, S.z, h & 1, h == 0, tid, nt);
+      __syncthreads();
+    }
+    // black cells were written by half sweep 2m-1; red by 2m
+    restrict_range(S.L, S.X, S.r, S.z, a.lv[k + 1].r, tid, nt);
+    __syncthreads();
+  };
+  auto coarse = [&]() {
+    SmallLevel<R>& C = a.lv[L];
+    for (int i = tid; i < a.ncoarse; i += nt) {
+      double s = 0.0;
+      for (int j = 0; j < a.ncoarse; ++j) s += a.Ainv[(long long)j * a.ncoarse + i] * (double)C.r[j];
+      C.x[i] = (R)s;
+    }
+    my_calls[L] += 1;
+    __syncthreads();
+  };
+  // post-smoothing of level k and one CG step; returns true when level k is done
+  auto post_step = [&](int k) -> bool {
+    SmallLevel<R>& S = a.lv[k];
+    prolong_range(S.L, S.X, a.lv[k + 1].x, S.z, tid, nt);
+    __syncthreads();
+    for (int h = 0; h <= 2 * a.m; ++h) {
+      gs_half_range(S.L, S.r, S.z, h & 1, false, tid, nt);
+      __syncthreads();
+    }
+    // rho = r.z
+    double acc = 0.0;
+    for (int c = tid; c < S.L.n; c += nt) acc += (double)S.r[c] * (double)S.z[c];
+    const double rho = block_sum(acc, sm);
+    const int it = sh_it[k];
+    if (!(rho > 0.0)) { status = -4; return true; }
+    const R beta = it == 0 ? R(0) : (R)(rho / sh_rho[k]);
+    for (int c = tid; c < S.L.n; c += nt) S.p[c] = it == 0 ? S.z[c] : S.z[c] + beta * S.p[c];
+    __syncthreads();
+    const double pq = block_sum(spmv_range<R, double>(S.L, S.p, S.q, tid, nt), sm);
+    if (!(pq > 0.0)) { status = -4; return true; }
+    const R alpha = (R)(rho / pq);
+    acc = 0.0;
+    for (int c = tid; c < S.L.n; c += nt) {
+      S.x[c] += alpha * S.p[c];
+      const R v = S.r[c] - alpha * S.q[c];
+      S.r[c] = v;
+      acc += (double)v * (double)v;
+    }
+    const double rr = block_sum(acc, sm);
+    if (tid == 0) { sh_rho[k] = rho; sh_rr[k] = rr; sh_it[k] = it + 1; }
+    my_iters[k] += 1;
+    __syncthreads();
+    return rr < sh_tol[k] || it + 1 >= a.max_inner;
+  };
+
+  int k = a.ks;
+  if (start(k)) goto done;
+  for (;;) {
+    // descend: begin an iteration at level k
+    pre(k);
+    if (k + 1 == L) {
+      coarse();
+    } else {
+      ++k;
+      if (!start(k)) continue;  // iterate on the deeper level
+      --k;                      // deeper level already converged: y = 0
+    }
+    // ascend: finish iterations up the stack
+    for (;;) {
+      const bool fin = post_step(k);
+      if (status) goto done;
+      if (!fin) break;  // next iteration at level k
+      if (k == a.ks) goto done;
+      --k;
+    }
+  }
+done:
+  if (tid == 0) {
+    for (int l = 0; l < kMaxLevels; ++l) {
+      a.iters[l] += my_iters[l];
+      a.calls[l] += my_calls[l];
+    }
+    if (status) a.status[0] = status;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s) {
+  const long long tot = (long long)(a.nx + 1) * a.ny * a.nz + (long long)a.nx * (a.ny + 1) * a.nz +
+                        (a.dim == 3 ? (long long)a.nx * a.ny * (a.nz + 1) : 0);
+  hipLaunchKernelGGL(k_face_T, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_positive(const double* k, long long n, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_positive, dim3(grid_for(n, 2048)), dim3(256), 0, s, k, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s) {
+  int ce[3] = {a.cd[0], a.cd[1], a.cd[2]};
+  ce[a.axis] += 1;
+  const long long tot = (long long)ce[0] * ce[1] * ce[2];
+  hipLaunchKernelGGL(k_coarsen_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 4096)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Y, double* Ainv, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
+  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, A, Y, Ainv, L.n, status);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_spmv(const Lv<R>& L, const R* x, R* y, double* part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv_dot<R>, dim3(nparts), dim3(kBlock), 0, s, L, x, y, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_residual(const Lv<R>& L, const R* b, const R* x, R* r, double* part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual<R>, dim3(nparts), dim3(kBlock), 0, s, L, b, x, r, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dot(const R* a, const R* b, int n, double* part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<R>, dim3(nparts), dim3(kBlock), 0, s, a, b, n, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_update_p(const R* z, R* p, int n, const Scal* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p<R>, dim3(grid_for(n)), dim3(kBlock), 0, s, z, p, n, sc);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_cg_update(R* x, R* r, const R* p, const R* q, int n, const Scal* sc, double* part, int nparts,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update<R>, dim3(nparts), dim3(kBlock), 0, s, x, r, p, q, n, sc, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s) {
+  const long long tot = (long long)((L.nx + 1) / 2) * L.ny * L.nz;
+  hipLaunchKernelGGL(k_gs_half<R>, dim3(grid_for(tot, 1 << 20)), dim3(kBlock), 0, s, L, r, x, colour, first);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s) {
+  const long long nc = (long long)X.cnx * X.cny * X.cnz;
+  hipLaunchKernelGGL(k_restrict<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X, r, x, g);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_solve<R>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Ainv, g, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const RhsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_init_x, dim3((n + 255) / 256), dim3(256), 0, s, x, n, nx, hx, Lx, p0, p1, ramp);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fill(R* a, long long n, R v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<R>, dim3(grid_for(n, 4096)), dim3(256), 0, s, a, n, v);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_copy(const R* a, R* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy<R>, dim3(grid_for(n, 4096)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(const double* a, float* b, int n, const Scal* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f64(const float* a, double* b, int n, const Scal* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_to_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, n, sc);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
+  SmallArgs<R> a{};
+  for (int l = 0; l < d.nlev; ++l) {
+    a.lv[l].L = d.L[l];
+    a.lv[l].X = d.X[l];
+    a.lv[l].x = d.x[l];
+    a.lv[l].r = d.r[l];
+    a.lv[l].z = d.z[l];
+    a.lv[l].p = d.p[l];
+    a.lv[l].q = d.q[l];
+    a.lv[l].tol = d.tol[l];
+  }
+  a.ks = d.ks;
+  a.nlev = d.nlev;
+  a.m = d.m;
+  a.max_inner = d.max_inner;
+  a.rel_floor2 = d.rel_floor2;
+  a.Ainv = d.Ainv;
+  a.ncoarse = d.ncoarse;
+  a.iters = d.iters;
+  a.calls = d.calls;
+  a.status = d.status;
+  hipLaunchKernelGGL(k_small_pcg<R>, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+#define MSCG_INST(R)                                                                                              \
+  template hipError_t launch_spmv<R>(const Lv<R>&, const R*, R*, double*, int, hipStream_t);                      \
+  template hipError_t launch_residual<R>(const Lv<R>&, const R*, const R*, R*, double*, int, hipStream_t);        \
+  template hipError_t launch_dot<R>(const R*, const R*, int, double*, int, hipStream_t);                          \
+  template hipError_t launch_update_p<R>(const R*, R*, int, const Scal*, hipStream_t);                            \
+  template hipError_t launch_cg_update<R>(R*, R*, const R*, const R*, int, const Scal*, double*, int, hipStream_t); \
+  template hipError_t launch_gs_half<R>(const Lv<R>&, const R*, R*, int, int, hipStream_t);                      \
+  template hipError_t launch_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, hipStream_t);         \
+  template hipError_t launch_prolong<R>(const Lv<R>&, const Xfer&, const R*, R*, hipStream_t);                    \
+  template hipError_t launch_coarse_solve<R>(const double*, const R*, R*, int, hipStream_t);                      \
+  template hipError_t launch_fill<R>(R*, long long, R, hipStream_t);                                              \
+  template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);                                       \
+  template hipError_t launch_small_pcg<R>(const SmallDesc<R>&, hipStream_t);
+
+MSCG_INST(double)
+MSCG_INST(float)
+template hipError_t launch_fill<int>(int*, long long, int, hipStream_t);
+template hipError_t launch_fill<long long>(long long*, long long, long long, hipStream_t);
+
+}  // namespace mscg

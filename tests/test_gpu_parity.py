@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Operators element by element, then full solves: relative residual <= 1e-10,
+solution within 1e-8 relative of the oracle's, outer iterations within 2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_math_9809043_amd import synth
+
+from conftest import gpu_available
+from test_oracle_pins import rhs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev_tensor(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def make_problem(P, **opt):
+    from paper_math_9809043_amd import mscg
+    grid = mscg.Grid(dim=P.dim, n=P.n, bc_type=P.bc_type, bc_value=P.bc_value, length=P.length)
+    prob = mscg.Problem(grid, mscg.Options(**opt))
+    prob.set_permeability(dev_tensor(P.kx), dev_tensor(P.ky), dev_tensor(P.kz) if P.dim == 3 else None)
+    return prob
+
+
+def gpu_solve(P, tol=None, **opt):
+    torch = _torch()
+    prob = make_problem(P, **opt)
+    p = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    st = prob.solve(dev_tensor(P.f), p, P.tol if tol is None else tol)
+    torch.cuda.synchronize()
+    return st, p.cpu().numpy(), prob
+
+
+def case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def oracle_opts(opt):
+    out = {}
+    if "interp" in opt:
+        out["interp"] = opt["interp"]
+    if "min_coarse_side" in opt:
+        out["min_side"] = opt["min_coarse_side"]
+    if "max_levels" in opt:
+        out["max_levels"] = opt["max_levels"]
+    return out
+
+
+# ------------------------------------------------------------------ operators
+
+HIER_CASES = [
+    ("small32", lambda: synth.small_case(0), {}),
+    ("ragged96x40", lambda: synth.smoothed_lognormal_2d(4, 96, 40, lo=-3, hi=3), {}),
+    ("channel128", lambda: synth.channelised_2d(1, 128), {"interp": 1}),
+    ("layered32", lambda: synth.layered_3d(2, 32, n_layers=8), {"interp": 1}),
+    ("smooth512", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {}),
+]
+
+
+@pytest.mark.parametrize("name,make,opt", HIER_CASES, ids=[c[0] for c in HIER_CASES])
+def test_transmissibility_hierarchy(name, make, opt):
+    case(f"hierarchy {name}")
+    P = make()
+    prob = make_problem(P, **opt)
+    ref = oracle.hierarchy_T(P, min_side=opt.get("min_coarse_side", 8))
+    assert prob.n_levels == len(ref)
+    for lvl, (dims, tx, ty, tz) in enumerate(ref):
+        assert prob.level_dims(lvl) == dims
+        gx, gy, gz = prob.transmissibility(lvl)
+        for g, r in ((gx, tx), (gy, ty), (gz, tz)):
+            if r is None:
+                continue
+            g = g.cpu().numpy()
+            assert np.allclose(g, r, rtol=1e-13, atol=0), (lvl, np.abs(g - r).max())
+
+
+@pytest.mark.parametrize("name,make,opt", HIER_CASES[:4], ids=[c[0] for c in HIER_CASES[:4]])
+def test_operator_smoother_transfers(name, make, opt):
+    case(f"operators {name}")
+    torch = _torch()
+    P = make()
+    prob = make_problem(P, **opt)
+    ref = oracle.hierarchy_T(P, min_side=opt.get("min_coarse_side", 8))
+    rng = np.random.default_rng(11)
+    interp = opt.get("interp", 0)
+    for lvl, (dims, tx, ty, tz) in enumerate(ref):
+        n = dims[0] * dims[1] * dims[2]
+        T = (tx, ty, tz)
+        x = rng.standard_normal(n)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        prob.apply_operator(lvl, dev_tensor(x), y)
+        ya = oracle.apply_A(P.dim, dims, T, x)
+        assert np.allclose(y.cpu().numpy(), ya, rtol=0, atol=1e-13 * np.abs(ya).max())
+        r = rng.standard_normal(n)
+        x0 = rng.standard_normal(n)
+        xs = dev_tensor(x0)
+        prob.apply_smoother(lvl, dev_tensor(r), xs, 4)
+        xo = oracle.sgs(P.dim, dims, T, r, x0, 4)
+        assert np.allclose(xs.cpu().numpy(), xo, rtol=0, atol=1e-11 * np.abs(xo).max())
+        if lvl + 1 < len(ref):
+            cd = ref[lvl + 1][0]
+            s = (dims[0] // cd[0], dims[1] // cd[1], dims[2] // cd[2])
+            nc = cd[0] * cd[1] * cd[2]
+            g = torch.empty(nc, dtype=torch.float64, device="cuda")
+            prob.restrict_residual(lvl, dev_tensor(r), dev_tensor(x0), g)
+            res = r - oracle.apply_A(P.dim, dims, T, x0)
+            go = oracle.restrict(P.dim, dims, s, res, interp)
+            assert np.allclose(g.cpu().numpy(), go, rtol=0, atol=1e-12 * np.abs(go).max())
+            yc = rng.standard_normal(nc)
+            xf = dev_tensor(x0)
+            prob.prolong_add(lvl, dev_tensor(yc), xf)
+            xo = oracle.prolong_add(P.dim, dims, s, yc, x0, interp)
+            assert np.allclose(xf.cpu().numpy(), xo, rtol=0, atol=1e-14 * np.abs(xo).max())
+
+
+@pytest.mark.parametrize("name,make,opt", [HIER_CASES[0], HIER_CASES[2], HIER_CASES[3]],
+                         ids=["small32", "channel128", "layered32"])
+def test_preconditioner(name, make, opt):
+    case(f"preconditioner {name}")
+    torch = _torch()
+    P = make()
+    prob = make_problem(P, **opt)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(P.N)
+    z = torch.empty(P.N, dtype=torch.float64, device="cuda")
+    # eps2 = 0: inner levels run to their iteration cap; small iteration cap keeps it cheap
+    eps2 = 1e-3
+    prob.apply_preconditioner(dev_tensor(r), z, eps2)
+    zo = oracle.precond(P, r, eps2=eps2, **oracle_opts(opt))
+    assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) < 1e-9
+
+
+# ------------------------------------------------------------------ full solves
+
+SOLVE_CASES = [(f"small32_s{s}", (lambda s=s: synth.small_case(s)), {}) for s in range(10)] + [
+    ("small32_fonly", lambda: synth.smoothed_lognormal_2d(3, 32, bc_value=(0.0, 0.0)), {}),
+    ("ragged96x40", lambda: synth.smoothed_lognormal_2d(4, 96, 40, lo=-3, hi=3), {}),
+    ("rect128x64", lambda: synth.smoothed_lognormal_2d(6, 128, 64, lo=-2, hi=2), {}),
+    ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
+    ("smooth512", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {}),
+    ("smooth256_const", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"interp": 1}),
+    ("channel64_const", lambda: synth.channelised_2d(0, 64), {"interp": 1}),
+    ("layered32_const", lambda: synth.layered_3d(2, 32, n_layers=8), {"interp": 1}),
+]
+
+
+@pytest.mark.parametrize("name,make,opt", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_parity(name, make, opt):
+    case(f"solve {name}")
+    P = make()
+    st, x, _ = gpu_solve(P, **opt)
+    ref = oracle.solve(P, **oracle_opts(opt))
+    err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+    print(f"  gpu outer={st.outer_iters} levels={st.level_iters} res={st.rel_residual_true:.2e} | "
+          f"oracle outer={ref.outer_iters} levels={ref.level_iters} | rel err {err:.2e}", flush=True)
+    assert ref.status == 0
+    assert st.status == 0
+    assert st.rel_residual_true <= 1e-10
+    assert err <= 1e-8
+    assert abs(st.outer_iters - ref.outer_iters) <= 2
+    # residual of the GPU result recomputed on the CPU from the oracle's operator
+    h = tuple(P.length[a] / P.n[a] for a in range(3))
+    T = oracle.face_T(P.dim, P.n, h, P.kx, P.ky, P.kz, P.bc_type)
+    b = rhs(P, *T)
+    Ax = oracle.apply_A(P.dim, P.n, T, x)
+    assert np.linalg.norm(Ax - b) / np.linalg.norm(b) <= 1.5e-10
+
+
+def test_single_level_direct_solve():
+    case("solve single level 16x16 direct")
+    P = synth.smoothed_lognormal_2d(2, 16)
+    st, x, prob = gpu_solve(P)
+    assert prob.n_levels == 1 and st.outer_iters == 0
+    ref = oracle.solve(P)
+    assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) < 1e-10
+
+
+def test_constant_K_linear_ramp():
+    case("solve constant K ramp")
+    P = synth.small_case(0)
+    P.kx[:] = 2.5
+    P.ky[:] = 2.5
+    P.f[:] = 0.0
+    st, x, _ = gpu_solve(P)
+    xc = (np.arange(32) + 0.5) / 32
+    assert st.outer_iters == 0
+    assert np.abs(x.reshape(32, 32) - xc[None, :]).max() < 1e-14
+
+
+# ------------------------------------------------------------------ errors
+
+def test_error_paths():
+    case("error paths")
+    torch = _torch()
+    from paper_math_9809043_amd import mscg
+    P = synth.small_case(0)
+    grid = mscg.Grid(dim=2, n=P.n, bc_type=P.bc_type, bc_value=P.bc_value)
+    prob = mscg.Problem(grid)
+    f = dev_tensor(P.f)
+    p = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(mscg.MscgError, match="E_STATE"):
+        prob.solve(f, p, 1e-10)
+    bad = P.kx.copy()
+    bad[17] = -1.0
+    with pytest.raises(mscg.MscgError, match="E_ARG"):
+        prob.set_permeability(dev_tensor(bad))
+    bad[17] = np.nan
+    with pytest.raises(mscg.MscgError, match="E_ARG"):
+        prob.set_permeability(dev_tensor(bad))
+    neu = mscg.Problem(mscg.Grid(dim=2, n=P.n, bc_type=[0] * 6))
+    with pytest.raises(mscg.MscgError, match="E_SINGULAR"):
+        neu.set_permeability(dev_tensor(P.kx))
+    capped = mscg.Problem(grid, mscg.Options(max_outer_iters=1))
+    capped.set_permeability(dev_tensor(P.kx), dev_tensor(P.ky))
+    st = capped.solve(f, p, 1e-10)
+    assert st.status == mscg.NOT_CONVERGED and st.outer_iters == 1 and st.rel_residual_true > 1e-10
+
+
+def test_batch_matches_single():
+    case("batch of mixed sizes")
+    torch = _torch()
+    from paper_math_9809043_amd import mscg
+    Ps = [synth.request_problem(synth.Request(i, 0.0, side, 1000 + i)) for i, side in enumerate((64, 128, 64, 256))]
+    probs, fs, ps, singles = [], [], [], []
+    for P in Ps:
+        prob = make_problem(P)
+        probs.append(prob)
+        fs.append(dev_tensor(P.f))
+        ps.append(torch.zeros(P.N, dtype=torch.float64, device="cuda"))
+        q = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        prob.solve(fs[-1], q, P.tol)
+        singles.append(q.cpu().numpy())
+    stats = mscg.solve_batch(probs, fs, ps, [P.tol for P in Ps])
+    torch.cuda.synchronize()
+    for st, p, s in zip(stats, ps, singles):
+        assert st.status == 0 and st.rel_residual_true <= 1e-8
+        assert np.array_equal(p.cpu().numpy(), s)
