@@ -194,6 +194,14 @@ int read_scal(mscg_problem* P, int k) {
   return MSCG_OK;
 }
 
+// Device scalars live in the caller's workspace, whose contents are arbitrary.
+int clear_scalars(mscg_problem* P) {
+  static_assert(sizeof(Scal) % sizeof(double) == 0, "Scal is cleared as doubles");
+  for (int l = 0; l < P->nlev; ++l)
+    HIP_TRY(launch_fill<double>(reinterpret_cast<double*>(P->lev[l].sc), sizeof(Scal) / sizeof(double), 0.0, P->stream));
+  return MSCG_OK;
+}
+
 int set_tol(mscg_problem* P, int k, double tol) {
   // the tolerance lives in device scalars; a one-element fill keeps it stream ordered
   HIP_TRY(launch_fill<double>(&P->lev[k].sc->tol, 1, tol, P->stream));
@@ -585,6 +593,8 @@ static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_to
   P->tol_scale = 1.0;
   HIP_TRY(launch_fill<long long>(P->dcount, 2 * MSCG_MAX_LEVELS, 0, P->stream));
   HIP_TRY(launch_fill<int>(P->dflags + 2, 1, 0, P->stream));
+  int rc = clear_scalars(P);
+  if (rc) return rc;
   // right-hand side and tolerance
   RhsArgs ra{};
   ra.dim = P->g.dim; ra.nx = L0.nx; ra.ny = L0.ny; ra.nz = L0.nz; ra.n = N;
@@ -596,7 +606,7 @@ static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_to
   HIP_TRY(launch_rhs(ra, P->stream));
   HIP_TRY(launch_dot<double>(P->b, P->b, N, P->part, nb, P->stream));
   HIP_TRY(launch_finish(P->part, nb, L0.sc, kOpBB, P->stream));
-  int rc = read_scal(P, 0);
+  rc = read_scal(P, 0);
   if (rc) return rc;
   const double bb = P->hsc->bb;
   P->eps2 = rel_tol * rel_tol * bb / N;
@@ -755,7 +765,9 @@ int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, doubl
   LevelH& L0 = P->lev[0];
   HIP_TRY(launch_copy<double>(r, L0.r, L0.n, P->stream));
   HIP_TRY(launch_fill<long long>(P->dcount, 2 * MSCG_MAX_LEVELS, 0, P->stream));
-  int rc = apply_prec(P, 0);
+  int rc = clear_scalars(P);
+  if (rc) return rc;
+  rc = apply_prec(P, 0);
   if (rc) return rc;
   HIP_TRY(launch_copy<double>(L0.z, z, L0.n, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));

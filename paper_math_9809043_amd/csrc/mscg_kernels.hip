@@ -345,6 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ pa
     case kOpEntry:  // entry check of the level criterion
       sc->rr = s;
       sc->it = 0;
+      sc->status = 0;
       sc->converged = s < sc->tol ? 1 : 0;
       if (!(s == s) || s == INFINITY) sc->status = -4;
       break;

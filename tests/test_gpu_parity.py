@@ -134,11 +134,14 @@ def test_preconditioner(name, make, opt):
     rng = np.random.default_rng(5)
     r = rng.standard_normal(P.N)
     z = torch.empty(P.N, dtype=torch.float64, device="cuda")
-    # eps2 = 0: inner levels run to their iteration cap; small iteration cap keeps it cheap
     eps2 = 1e-3
     prob.apply_preconditioner(dev_tensor(r), z, eps2)
     zo = oracle.precond(P, r, eps2=eps2, **oracle_opts(opt))
-    assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) < 1e-9
+    # two levels: exact coarse solve, only rounding differs.  Three levels: an
+    # inner PCG on a 1e9-contrast operator amplifies the rounding differences of
+    # its reductions by its condition number (~1e9 * 1e-16).
+    tol = 1e-10 if prob.n_levels == 2 else 1e-6
+    assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) < tol
 
 
 # ------------------------------------------------------------------ full solves
