@@ -1,0 +1,162 @@
+"""Benchmark: unknowns solved per second to 1e-10 relative residual on one MI355X.
+
+One step = the whole hot path on one synthetic problem already resident in
+HBM: face transmissibilities, coarse graining and coarsest factorisation
+(mscg_set_permeability), then the recursive multi-scale PCG solve
+(mscg_solve).  Prints one JSON line.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload smooth1024|layered128|channel1024]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    # 2-D, the paper's base-case contrast (1e6) at the 1024^2 size
+    "smooth1024": dict(desc="2-D 5-point FV -div(k grad p)=f, 1024x1024 (1,048,576 unknowns); log10 k ~ U[-3,3] "
+                            "i.i.d. then 3x3 box-smoothed (contrast 1e6); Dirichlet p=0/1 on x, no-flow on y; "
+                            "f ~ N(0,1); tol 1e-10; levels 1024,256,64,16 (dense FP64 coarsest)",
+                       make="smooth", opt={}),
+    "layered128": dict(desc="3-D 7-point FV, 128^3 (2,097,152 unknowns); 16 layers of log10 kx = log10 ky ~ "
+                            "U[-3,3], kz = kx/100; Dirichlet on the x faces; f ~ N(0,1); tol 1e-10; "
+                            "piecewise-constant extension", make="layered", opt={"interp": 1}),
+    "channel1024": dict(desc="2-D, 1024x1024, 8x8-cell blocks of log10 k ~ U[-4.5,4.5] plus 5 channels "
+                             "(contrast 1e9); tol 1e-10; piecewise-constant extension", make="channel",
+                        opt={"interp": 1}),
+}
+
+
+def make_problem(kind, seed=0):
+    from paper_math_9809043_amd import synth
+    if kind == "smooth":
+        return synth.smoothed_lognormal_2d(seed, 1024, lo=-3.0, hi=3.0, tol=1e-10, name="smooth1024")
+    if kind == "layered":
+        return synth.layered_128(seed)
+    if kind == "channel":
+        return synth.channel_1024(seed)
+    raise ValueError(kind)
+
+
+def run_gpu(P, opt, steps, warmup):
+    import torch
+    from paper_math_9809043_amd import mscg
+    dev = torch.device("cuda:0")
+    grid = mscg.Grid(dim=P.dim, n=P.n, bc_type=P.bc_type, bc_value=P.bc_value, length=P.length)
+    prob = mscg.Problem(grid, mscg.Options(**opt), device=dev)
+    kx = torch.tensor(P.kx, device=dev)
+    ky = torch.tensor(P.ky, device=dev)
+    kz = torch.tensor(P.kz, device=dev) if P.dim == 3 else None
+    f = torch.tensor(P.f, device=dev)
+    p = torch.zeros(P.N, dtype=torch.float64, device=dev)
+
+    def step():
+        prob.set_permeability(kx, ky, kz)
+        return prob.solve(f, p, P.tol)
+
+    for _ in range(warmup):
+        st = step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    stats = []
+    for _ in range(steps):
+        stats.append(step())
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall_ms = (t1 - t0) * 1e3 / steps
+    solve_ms = sum(s.solve_ms for s in stats) / steps
+    st = stats[-1]
+    return prob, st, wall_ms, solve_ms, p
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="smooth1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one process, one MI355X).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_math_9809043_amd import mscg
+
+    W = WORKLOADS[args.workload]
+    P = make_problem(W["make"])
+    print(f"[bench] workload {args.workload}: {P.N} unknowns, steps {args.steps}, warmup {args.warmup}", flush=True)
+    prob, st, wall_ms, solve_ms, p = run_gpu(P, W["opt"], args.steps, args.warmup)
+    print(f"[bench] fp64: {wall_ms:.2f} ms/step (solve {solve_ms:.2f} ms) outer {st.outer_iters} "
+          f"levels {st.level_iters} res {st.rel_residual_true:.2e} status {st.status}", flush=True)
+
+    # dominant kernel: the finest-level red-black half sweep (2(2m+1) launches per outer iteration)
+    us, nbytes = prob.time_kernel(mscg.KERNEL_SMOOTH_HALF, 0, reps=50)
+    achieved = nbytes / (us * 1e-6) / 1e9
+    sp_us, sp_bytes = prob.time_kernel(mscg.KERNEL_SPMV, 0, reps=50)
+    roofline = {"bound": "hbm", "kernel": "k_gs_half<double> (finest level)", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None, "avg_us": round(us, 3), "alg_bytes_per_launch": int(nbytes),
+                "spmv": {"avg_us": round(sp_us, 3), "achieved": round(sp_bytes / (sp_us * 1e-6) / 1e9, 1)}}
+
+    mixed = None
+    if not args.no_mixed:
+        opt = dict(W["opt"])
+        opt["precision"] = mscg.MIXED
+        _, mst, mwall, msolve, _ = run_gpu(P, opt, args.steps, args.warmup)
+        mixed = {"value": round(P.N / (mwall * 1e-3), 1), "ms_per_step": round(mwall, 3),
+                 "solve_ms": round(msolve, 3), "outer_iters": mst.outer_iters, "level_iters": mst.level_iters,
+                 "rel_residual_true": mst.rel_residual_true, "status": mst.status,
+                 "speedup_vs_fp64": round(wall_ms / mwall, 3)}
+        print(f"[bench] mixed: {mwall:.2f} ms/step outer {mst.outer_iters} res {mst.rel_residual_true:.2e}",
+              flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.solve(P, **({"interp": W["opt"]["interp"]} if "interp" in W["opt"] else {}))
+        t1 = time.perf_counter()
+        cpu = {"value": round(P.N / (t1 - t0), 1), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full set-up + solve of the same {args.workload} problem by the serial FP64 C "
+                         f"oracle ({t1 - t0:.1f} s, {ref.outer_iters} outer iterations)"}
+        import numpy as np
+        x = p.cpu().numpy()
+        cpu["gpu_rel_err_vs_oracle"] = float(np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p))
+        print(f"[bench] oracle: {t1 - t0:.2f} s", flush=True)
+
+    value = P.N / (wall_ms * 1e-3)
+    line = {
+        "metric": "unknowns solved/s to 1e-10 resid (set-up + solve), FP64 plain method; mixed alongside",
+        "value": round(value, 1), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["desc"], "unknowns": P.N, "outer_iters": st.outer_iters,
+                   "level_iters": st.level_iters, "rel_residual_true": st.rel_residual_true,
+                   "solve_only_ms": round(solve_ms, 3)},
+        "mixed": mixed,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

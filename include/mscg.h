@@ -174,6 +174,24 @@ int mscg_prolong_add(mscg_problem *prob, int level, const double *y_coarse, doub
  * max_inner_iters).  FP64 problems only. */
 int mscg_apply_preconditioner(mscg_problem *prob, const double *r, double *z, double eps2);
 
+/* ---- Measurement ---- */
+
+enum {
+  MSCG_KERNEL_SMOOTH_HALF = 0, /* one red-black Gauss-Seidel half sweep */
+  MSCG_KERNEL_SPMV = 1,        /* q = A p with the partial sums of p.q */
+  MSCG_KERNEL_RESTRICT = 2,    /* g = R (r - A x) */
+  MSCG_KERNEL_PROLONG = 3,     /* x += E y */
+  MSCG_KERNEL_CG_UPDATE = 4    /* x += alpha p, r -= alpha q with partial |r|^2 */
+};
+
+/* Launches one solver kernel `reps` times back to back on the problem's
+ * stream, with the launch configuration the solver uses on `level`, and
+ * reports its average duration (HIP events) and its algorithmic bytes per
+ * launch: every operand array read once and written once.  Operates on the
+ * problem's own work vectors (their contents are overwritten).  Needs
+ * mscg_set_permeability; run a solve first so the vectors hold finite values. */
+int mscg_time_kernel(mscg_problem *prob, int kernel, int level, int reps, double *avg_us, double *alg_bytes);
+
 #ifdef __cplusplus
 }
 #endif

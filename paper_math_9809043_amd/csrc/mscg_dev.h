@@ -192,6 +192,36 @@ __device__ __forceinline__ void restrict_range(const Lv<R>& F, const Xfer& X, co
   }
 }
 
+// g_coarse = E^T res for coarse cells [t0, nc) step nt, res already stored
+// (no stencil evaluation in the footprint loop).
+template <typename R>
+__device__ __forceinline__ void restrict_stored_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ res,
+                                                      R* __restrict__ g, int t0, int nt) {
+  const int nc = X.cnx * X.cny * X.cnz;
+  for (int C = t0; C < nc; C += nt) {
+    int I, J, K;
+    cell_ijk(C, X.cnx, X.cny, I, J, K);
+    int ilo, ihi, jlo, jhi, klo, khi;
+    ext_support(I, X.sx, F.nx, X.interp, ilo, ihi);
+    ext_support(J, X.sy, F.ny, X.interp, jlo, jhi);
+    ext_support(K, X.sz, F.nz, X.interp, klo, khi);
+    R acc = R(0);
+    for (int k = klo; k <= khi; ++k) {
+      const R wk = ext_weight_of<R>(k, K, X.sz, X.cnz, X.interp);
+      if (wk == R(0)) continue;
+      for (int j = jlo; j <= jhi; ++j) {
+        const R wj = ext_weight_of<R>(j, J, X.sy, X.cny, X.interp);
+        if (wj == R(0)) continue;
+        const R* row = res + F.nx * (j + F.ny * k);
+        R racc = R(0);
+        for (int i = ilo; i <= ihi; ++i) racc += ext_weight_of<R>(i, I, X.sx, X.cnx, X.interp) * row[i];
+        acc += (wk * wj) * racc;
+      }
+    }
+    g[C] = acc;
+  }
+}
+
 // x_fine += E y_coarse for fine cells [t0, n) step nt.
 template <typename R>
 __device__ __forceinline__ void prolong_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ y,

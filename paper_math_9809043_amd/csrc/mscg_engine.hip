@@ -77,7 +77,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   for (int f = 0; f < 6; ++f)
     if (g->bc_type[f] != MSCG_NEUMANN && g->bc_type[f] != MSCG_DIRICHLET)
       return fail(MSCG_E_ARG, "bc_type[%d] must be MSCG_NEUMANN or MSCG_DIRICHLET", f);
-  if (o->scale < 2) return fail(MSCG_E_ARG, "scale must be >= 2");
+  if (o->scale < 2 || o->scale > 8) return fail(MSCG_E_ARG, "scale must be in [2, 8]");
   if (o->smooth_steps < 1) return fail(MSCG_E_ARG, "smooth_steps must be >= 1");
   if (!(o->level_factor > 0.0)) return fail(MSCG_E_ARG, "level_factor must be > 0");
   if (o->interp != MSCG_INTERP_LINEAR && o->interp != MSCG_INTERP_CONSTANT) return fail(MSCG_E_ARG, "bad interp");
@@ -113,12 +113,12 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
     if (mixed) { add(fx * 4); add(fy * 4); if (fz) add(fz * 4); }
     const bool fp64_vec = !mixed || l == 0;
     for (int v = 0; v < 5; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
-    if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, smoother iterate
+    if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, iterate, residual
     add(sizeof(Scal));
   }
   add((size_t)P->lv[0].n * 8);  // b
   const size_t nc = (size_t)P->lv[nl - 1].n;
-  add(nc * nc * 8); add(nc * nc * 8); add(nc * nc * 8);  // A, Y, A^-1
+  add(nc * nc * 8); add(nc * nc * 8);  // A (then its factor), A^-1
   add((size_t)kMaxPartials * 8);
   add(64);                                              // flags
   add(2 * MSCG_MAX_LEVELS * sizeof(long long));         // small-kernel counters
@@ -146,7 +146,7 @@ struct mscg_problem {
   int device;
   int nlev, ks;
   LevelH lev[MSCG_MAX_LEVELS];
-  double *Atmp, *Ytmp, *Ainv;
+  double *Atmp, *Ainv;
   int ncoarse;
   double* part;
   double* b;
@@ -258,7 +258,7 @@ int precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* co
                  R* const* ps, R* const* qs) {
   const int m = P->o.smooth_steps;
   for (int h = 0; h <= 2 * m; ++h) HIP_TRY(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream));
-  HIP_TRY(launch_restrict<R>(L, xfer(P, k), r, z, rs[k + 1], P->stream));
+  HIP_TRY(launch_residual_restrict<R>(L, xfer(P, k), r, z, qs[k], rs[k + 1], P->stream));
   int rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
   if (rc) return rc;
   HIP_TRY(launch_prolong<R>(L, xfer(P, k), xs[k + 1], z, P->stream));
@@ -384,13 +384,16 @@ int carve(mscg_problem* P, const Plan& plan) {
       L.x32 = (float*)take((size_t)L.n * 4); L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4);
       L.p32 = (float*)take((size_t)L.n * 4); L.q32 = (float*)take((size_t)L.n * 4);
     }
-    if (mx && l == 0) { L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4); }
+    if (mx && l == 0) {
+      L.r32 = (float*)take((size_t)L.n * 4);
+      L.z32 = (float*)take((size_t)L.n * 4);
+      L.q32 = (float*)take((size_t)L.n * 4);
+    }
     L.sc = (Scal*)take(sizeof(Scal));
   }
   P->b = (double*)take((size_t)plan.lv[0].n * 8);
   const size_t nc = (size_t)plan.lv[plan.nlev - 1].n;
   P->Atmp = (double*)take(nc * nc * 8);
-  P->Ytmp = (double*)take(nc * nc * 8);
   P->Ainv = (double*)take(nc * nc * 8);
   P->ncoarse = (int)nc;
   P->part = (double*)take((size_t)kMaxPartials * 8);
@@ -572,7 +575,7 @@ int mscg_set_permeability(mscg_problem* P, const double* kx, const double* ky, c
     }
   }
   // coarsest factorisation
-  HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Ytmp, P->Ainv, P->dflags, P->stream));
+  HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Ainv, P->dflags, P->stream));
   HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   if (P->hflags[0]) {
@@ -772,6 +775,66 @@ int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, doubl
   HIP_TRY(launch_copy<double>(L0.z, z, L0.n, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return P->status;
+}
+
+int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* avg_us, double* alg_bytes) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level out of range");
+  if (reps < 1) return fail(MSCG_E_ARG, "reps must be >= 1");
+  if ((kernel == MSCG_KERNEL_RESTRICT || kernel == MSCG_KERNEL_PROLONG) && level + 1 >= P->nlev)
+    return fail(MSCG_E_ARG, "transfer kernels need a coarser level");
+  const bool fp32 = mixed(P) && level > 0;
+  if (fp32 && kernel != MSCG_KERNEL_SMOOTH_HALF) return fail(MSCG_E_ARG, "FP32 timing covers the smoother only");
+  LevelH& L = P->lev[level];
+  const double w = fp32 ? 4.0 : 8.0;
+  const double n = L.n;
+  const double faces = (double)(L.nx + 1) * L.ny * L.nz + (double)L.nx * (L.ny + 1) * L.nz +
+                       (P->g.dim == 3 ? (double)L.nx * L.ny * (L.nz + 1) : 0.0);
+  double bytes = 0.0;
+  const int nb = reduce_blocks(L.n);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto launch = [&]() -> hipError_t {
+    switch (kernel) {
+      case MSCG_KERNEL_SMOOTH_HALF:
+        if (fp32 || (mixed(P) && level == 0)) return launch_gs_half<float>(lv32(P, level), level == 0 ? L.r32 : L.r32, L.z32, 0, 0, P->stream);
+        return launch_gs_half<double>(lv64(P, level), L.r, L.z, 0, 0, P->stream);
+      case MSCG_KERNEL_SPMV:
+        return launch_spmv<double>(lv64(P, level), L.p, L.q, P->part, nb, P->stream);
+      case MSCG_KERNEL_RESTRICT:
+        return launch_restrict<double>(lv64(P, level), xfer(P, level), L.r, L.z, P->lev[level + 1].r, P->stream);
+      case MSCG_KERNEL_PROLONG:
+        return launch_prolong<double>(lv64(P, level), xfer(P, level), P->lev[level + 1].x, L.z, P->stream);
+      case MSCG_KERNEL_CG_UPDATE:
+        return launch_cg_update<double>(L.x, L.r, L.p, L.q, L.n, L.sc, P->part, nb, P->stream);
+      default:
+        return hipErrorInvalidValue;
+    }
+  };
+  const double ws = (mixed(P) && level == 0 && kernel == MSCG_KERNEL_SMOOTH_HALF) ? 4.0 : w;
+  switch (kernel) {
+    case MSCG_KERNEL_SMOOTH_HALF: bytes = ws * (faces + n + 0.5 * n + 0.5 * n); break;  // T, x, r (one colour), x (one colour)
+    case MSCG_KERNEL_SPMV: bytes = w * (faces + 2.0 * n); break;                       // T, p in; q out
+    case MSCG_KERNEL_RESTRICT: bytes = w * (faces + 2.0 * n + (double)P->lev[level + 1].n); break;
+    case MSCG_KERNEL_PROLONG: bytes = w * (2.0 * n + (double)P->lev[level + 1].n); break;
+    case MSCG_KERNEL_CG_UPDATE: bytes = w * 6.0 * n; break;                            // x, r, p, q in; x, r out
+    default: return fail(MSCG_E_ARG, "unknown kernel id %d", kernel);
+  }
+  HIP_TRY(launch());  // warm
+  HIP_TRY(hipEventRecord(e0, P->stream));
+  for (int i = 0; i < reps; ++i) HIP_TRY(launch());
+  HIP_TRY(hipEventRecord(e1, P->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (avg_us) *avg_us = 1000.0 * ms / reps;
+  if (alg_bytes) *alg_bytes = bytes;
+  return MSCG_OK;
 }
 
 }  // extern "C"

@@ -69,7 +69,7 @@ hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s);
 hipError_t launch_check_positive(const double* k, long long n, int* bad, hipStream_t s);
 hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s);
 hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
-hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Y, double* Ainv, int* status, hipStream_t s);
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Ainv, int* status, hipStream_t s);
 hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s);
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
 hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp, hipStream_t s);
@@ -91,6 +91,9 @@ template <typename R>
 hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s);
 template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s);
+template <typename R>
+hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* tmp, R* g,
+                                    hipStream_t s);
 template <typename R>
 hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s);
 template <typename R>

@@ -168,65 +168,81 @@ __global__ void k_dense_assemble(Lv<double> L, double* __restrict__ A) {
 }
 
 // Coarsest factorisation (Section 2.2/2.3: the recursion ends with an exact
-// solve): right-looking Cholesky A = L L^T in place (one workgroup), then
-// Y = L^-1 one column per thread, then A^-1 = Y^T Y, stored row-major so
-// y = A^-1 g is a coalesced matrix-vector product.  status[0] = 1 if A is not
+// solve).  A is symmetric, so its row-major assembly is also column-major;
+// the factor L (A = L L^T) overwrites the lower triangle in column-major
+// order, L[i][k] at A[k n + i], so a column is contiguous.  One workgroup,
+// right-looking: scale column j, then each wave updates whole trailing
+// columns with its lanes along i (coalesced).  status[0] = 1 if A is not
 // positive definite.
-__global__ void __launch_bounds__(1024) k_cholesky_inverse(double* __restrict__ A, double* __restrict__ Y,
-                                                           double* __restrict__ Ainv, int n, int* __restrict__ status) {
+__global__ void __launch_bounds__(1024) k_chol_factor(double* __restrict__ A, int n, int* __restrict__ status) {
   __shared__ int bad;
+  __shared__ double sd;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid / kWave, lane = tid % kWave, nw = nt / kWave;
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     if (tid == 0) {
       const double d = A[(long long)j * n + j];
       if (!(d > 0.0)) bad = 1;
-      A[(long long)j * n + j] = d > 0.0 ? sqrt(d) : 1.0;
+      sd = d > 0.0 ? sqrt(d) : 1.0;
+      A[(long long)j * n + j] = sd;
     }
     __syncthreads();
     if (bad) break;
-    const double djj = A[(long long)j * n + j];
-    for (int i = j + 1 + tid; i < n; i += nt) A[(long long)i * n + j] /= djj;
+    const double d = sd;
+    double* colj = A + (long long)j * n;
+    for (int i = j + 1 + tid; i < n; i += nt) colj[i] /= d;
     __syncthreads();
-    // trailing update of the lower triangle: rows i > j, columns j < l <= i
-    const long long m = n - j - 1;
-    const long long cnt = m * (m + 1) / 2;
-    for (long long e = tid; e < cnt; e += nt) {
-      // e -> (ii, ll) with 0 <= ll <= ii < m, row-major over the triangle
-      long long ii = (long long)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while (ii * (ii + 1) / 2 > e) --ii;
-      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      const long long ll = e - ii * (ii + 1) / 2;
-      const long long i = j + 1 + ii, l = j + 1 + ll;
-      A[i * n + l] -= A[i * n + j] * A[l * n + j];
+    for (int l = j + 1 + wave; l < n; l += nw) {
+      const double ljl = colj[l];
+      double* coll = A + (long long)l * n;
+      for (int i = l + lane; i < n; i += kWave) coll[i] -= colj[i] * ljl;
     }
     __syncthreads();
   }
-  if (bad) {
-    if (tid == 0) status[0] = 1;
-    return;
-  }
-  // Y = L^-1 (lower triangular), column c by thread c
-  for (int c = tid; c < n; c += nt) {
-    for (int i = 0; i < n; ++i) {
-      if (i < c) { Y[(long long)i * n + c] = 0.0; continue; }
-      double s = i == c ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= A[(long long)i * n + k] * Y[(long long)k * n + c];
-      Y[(long long)i * n + c] = s / A[(long long)i * n + i];
+  if (tid == 0) status[0] = bad;
+}
+
+// A^-1 from the factor: thread c solves L L^T x = e_c (forward, then
+// backward substitution) and writes column c of A^-1 (= row c by symmetry)
+// into Ainv[k n + c].  The loops run from the wave's first column so every
+// lane reads the same L entry (a broadcast); entries above c are zero.
+__global__ void __launch_bounds__(kWave) k_chol_inverse(const double* __restrict__ L, double* __restrict__ Ainv, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c0 = blockIdx.x * blockDim.x;
+  const bool on = c < n;
+  const int cc = on ? c : n - 1;
+  // forward: w = L^-1 e_c
+  for (int i = c0; i < n; ++i) {
+    double s0 = (i == cc) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = c0;
+    for (; k + 3 < i; k += 4) {
+      s0 -= L[(long long)k * n + i] * Ainv[(long long)k * n + cc];
+      s1 -= L[(long long)(k + 1) * n + i] * Ainv[(long long)(k + 1) * n + cc];
+      s2 -= L[(long long)(k + 2) * n + i] * Ainv[(long long)(k + 2) * n + cc];
+      s3 -= L[(long long)(k + 3) * n + i] * Ainv[(long long)(k + 3) * n + cc];
     }
+    for (; k < i; ++k) s0 -= L[(long long)k * n + i] * Ainv[(long long)k * n + cc];
+    const double w = ((s0 + s1) + (s2 + s3)) / L[(long long)i * n + i];
+    if (on) Ainv[(long long)i * n + c] = i < c ? 0.0 : w;
   }
-  __syncthreads();
-  // A^-1 = Y^T Y: (i, l) = sum_{k >= max(i,l)} Y[k][i] Y[k][l]
-  const long long nn = (long long)n * n;
-  for (long long e = tid; e < nn; e += nt) {
-    const int i = (int)(e / n), l = (int)(e % n);
-    const int k0 = i > l ? i : l;
-    double s = 0.0;
-    for (int k = k0; k < n; ++k) s += Y[(long long)k * n + i] * Y[(long long)k * n + l];
-    Ainv[e] = s;
+  // backward: x = L^-T w
+  for (int i = n - 1; i >= 0; --i) {
+    // rows above the wave's first column were not written by the forward
+    // pass: w is zero there
+    double s0 = i < c0 ? 0.0 : Ainv[(long long)i * n + cc], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = i + 1;
+    for (; k + 3 < n; k += 4) {
+      s0 -= L[(long long)i * n + k] * Ainv[(long long)k * n + cc];
+      s1 -= L[(long long)i * n + k + 1] * Ainv[(long long)(k + 1) * n + cc];
+      s2 -= L[(long long)i * n + k + 2] * Ainv[(long long)(k + 2) * n + cc];
+      s3 -= L[(long long)i * n + k + 3] * Ainv[(long long)(k + 3) * n + cc];
+    }
+    for (; k < n; ++k) s0 -= L[(long long)i * n + k] * Ainv[(long long)k * n + cc];
+    const double x = ((s0 + s1) + (s2 + s3)) / L[(long long)i * n + i];
+    if (on) Ainv[(long long)i * n + c] = x;
   }
-  if (tid == 0) status[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -261,6 +277,19 @@ __global__ void __launch_bounds__(kBlock) k_residual(Lv<R> L, const R* __restric
   }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// res = b - A x without a reduction
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_residual_nodot(Lv<R> L, const R* __restrict__ b, const R* __restrict__ x,
+                                                            R* __restrict__ res) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, L.nx, L.ny, i, j, k);
+    R d, o;
+    stencil_at(L, x, i, j, k, c, d, o);
+    res[c] = b[c] - (d * x[c] - o);
+  }
 }
 
 template <typename R>
@@ -312,6 +341,12 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_restrict(Lv<R> F, Xfer X, const R* __restrict__ r,
                                                       const R* __restrict__ x, R* __restrict__ g) {
   restrict_range(F, X, r, x, g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_restrict_stored(Lv<R> F, Xfer X, const R* __restrict__ res,
+                                                             R* __restrict__ g) {
+  restrict_stored_range(F, X, res, g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 template <typename R>
@@ -453,6 +488,7 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
   __shared__ double sm[1024 / kWave];
   __shared__ double sh_rho[kMaxLevels], sh_rr[kMaxLevels], sh_tol[kMaxLevels];
   __shared__ int sh_it[kMaxLevels];
+  __shared__ double sh_g[1024], sh_part[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int L = a.nlev - 1;  // coarsest index
   long long my_iters[kMaxLevels], my_calls[kMaxLevels];
@@ -482,15 +518,40 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
       gs_half_range(S.L, S.r, S.z, h & 1, h == 0, tid, nt);
       __syncthreads();
     }
-    // black cells were written by half sweep 2m-1; red by 2m
-    restrict_range(S.L, S.X, S.r, S.z, a.lv[k + 1].r, tid, nt);
+    // residual into q (free during the preconditioner), then g = E^T res
+    for (int c = tid; c < S.L.n; c += nt) {
+      int i, j, kk;
+      cell_ijk(c, S.L.nx, S.L.ny, i, j, kk);
+      R d, o;
+      stencil_at(S.L, S.z, i, j, kk, c, d, o);
+      S.q[c] = S.r[c] - (d * S.z[c] - o);
+    }
+    __syncthreads();
+    restrict_stored_range(S.L, S.X, (const R*)S.q, a.lv[k + 1].r, tid, nt);
     __syncthreads();
   };
+  // y = A^-1 g on the coarsest level: the columns of A^-1 are split into
+  // nt / nc groups whose partial sums are added in group order.
   auto coarse = [&]() {
     SmallLevel<R>& C = a.lv[L];
-    for (int i = tid; i < a.ncoarse; i += nt) {
+    const int nc = a.ncoarse;
+    for (int i = tid; i < nc; i += nt) sh_g[i] = (double)C.r[i];
+    __syncthreads();
+    const int groups = nc >= nt ? 1 : nt / nc;
+    const int per = (nc + groups - 1) / groups;
+    if (tid < groups * nc) {
+      for (int i = tid % nc; i < nc; i += nt) {
+        const int grp = tid / nc;
+        const int j0 = grp * per, j1 = j0 + per < nc ? j0 + per : nc;
+        double s = 0.0;
+        for (int j = j0; j < j1; ++j) s += a.Ainv[(long long)j * nc + i] * sh_g[j];
+        sh_part[grp * nc + i] = s;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nc; i += nt) {
       double s = 0.0;
-      for (int j = 0; j < a.ncoarse; ++j) s += a.Ainv[(long long)j * a.ncoarse + i] * (double)C.r[j];
+      for (int grp = 0; grp < groups; ++grp) s += sh_part[grp * nc + i];
       C.x[i] = (R)s;
     }
     my_calls[L] += 1;
@@ -593,9 +654,10 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Y, double* Ainv, int* status, hipStream_t s) {
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Ainv, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
-  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, A, Y, Ainv, L.n, status);
+  hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, A, L.n, status);
+  hipLaunchKernelGGL(k_chol_inverse, dim3((L.n + kWave - 1) / kWave), dim3(kWave), 0, s, A, Ainv, L.n);
   return hipGetLastError();
 }
 
@@ -641,6 +703,16 @@ template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s) {
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
   hipLaunchKernelGGL(k_restrict<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X, r, x, g);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* tmp, R* g,
+                                    hipStream_t s) {
+  const long long nc = (long long)X.cnx * X.cny * X.cnz;
+  hipLaunchKernelGGL(k_residual_nodot<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, r, x, tmp);
+  hipLaunchKernelGGL(k_restrict_stored<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X,
+                     (const R*)tmp, g);
   return hipGetLastError();
 }
 
@@ -729,6 +801,7 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
   template hipError_t launch_cg_update<R>(R*, R*, const R*, const R*, int, const Scal*, double*, int, hipStream_t); \
   template hipError_t launch_gs_half<R>(const Lv<R>&, const R*, R*, int, int, hipStream_t);                      \
   template hipError_t launch_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, hipStream_t);         \
+  template hipError_t launch_residual_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, R*, hipStream_t); \
   template hipError_t launch_prolong<R>(const Lv<R>&, const Xfer&, const R*, R*, hipStream_t);                    \
   template hipError_t launch_coarse_solve<R>(const double*, const R*, R*, int, hipStream_t);                      \
   template hipError_t launch_fill<R>(R*, long long, R, hipStream_t);                                              \

@@ -53,8 +53,9 @@ EXPORTS = [
     "mscg_default_options", "mscg_footprint_bytes", "mscg_create_problem", "mscg_set_permeability", "mscg_solve",
     "mscg_solve_batch", "mscg_destroy_problem", "mscg_last_error", "mscg_level_info", "mscg_get_transmissibility",
     "mscg_apply_operator", "mscg_apply_smoother", "mscg_restrict_residual", "mscg_prolong_add",
-    "mscg_apply_preconditioner",
+    "mscg_apply_preconditioner", "mscg_time_kernel",
 ]
+KERNEL_SMOOTH_HALF, KERNEL_SPMV, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_CG_UPDATE = range(5)
 
 _lib = None
 
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     L.mscg_prolong_add.restype = ctypes.c_int
     L.mscg_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_double]
     L.mscg_apply_preconditioner.restype = ctypes.c_int
+    L.mscg_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+    L.mscg_time_kernel.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -285,6 +288,12 @@ class Problem:
 
     def prolong_add(self, level: int, y, x):
         _check(self._L.mscg_prolong_add(self._h, level, _f64(y), _f64(x)))
+
+    def time_kernel(self, kernel: int, level: int = 0, reps: int = 20):
+        """(average microseconds per launch, algorithmic bytes per launch)."""
+        us, b = ctypes.c_double(), ctypes.c_double()
+        _check(self._L.mscg_time_kernel(self._h, kernel, level, reps, ctypes.byref(us), ctypes.byref(b)))
+        return us.value, b.value
 
     def apply_preconditioner(self, r, z, eps2: float = 0.0):
         _check(self._L.mscg_apply_preconditioner(self._h, _f64(r), _f64(z), float(eps2)), allow=(OK, E_BREAKDOWN))
