@@ -193,7 +193,10 @@ __device__ __forceinline__ void restrict_range(const Lv<R>& F, const Xfer& X, co
 }
 
 // g_coarse = E^T res for coarse cells [t0, nc) step nt, res already stored
-// (no stencil evaluation in the footprint loop).
+// (no stencil evaluation in the footprint loop).  The x weights of a coarse
+// cell are computed once into registers and reused for every fine row.
+constexpr int kMaxFoot = 20;  // >= 2s + 2 (linear) and >= s (constant) for s <= 8
+
 template <typename R>
 __device__ __forceinline__ void restrict_stored_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ res,
                                                       R* __restrict__ g, int t0, int nt) {
@@ -205,6 +208,9 @@ __device__ __forceinline__ void restrict_stored_range(const Lv<R>& F, const Xfer
     ext_support(I, X.sx, F.nx, X.interp, ilo, ihi);
     ext_support(J, X.sy, F.ny, X.interp, jlo, jhi);
     ext_support(K, X.sz, F.nz, X.interp, klo, khi);
+    R wx[kMaxFoot];
+#pragma unroll
+    for (int a = 0; a < kMaxFoot; ++a) wx[a] = (ilo + a <= ihi) ? ext_weight_of<R>(ilo + a, I, X.sx, X.cnx, X.interp) : R(0);
     R acc = R(0);
     for (int k = klo; k <= khi; ++k) {
       const R wk = ext_weight_of<R>(k, K, X.sz, X.cnz, X.interp);
@@ -212,9 +218,11 @@ __device__ __forceinline__ void restrict_stored_range(const Lv<R>& F, const Xfer
       for (int j = jlo; j <= jhi; ++j) {
         const R wj = ext_weight_of<R>(j, J, X.sy, X.cny, X.interp);
         if (wj == R(0)) continue;
-        const R* row = res + F.nx * (j + F.ny * k);
+        const R* row = res + F.nx * (j + F.ny * k) + ilo;
         R racc = R(0);
-        for (int i = ilo; i <= ihi; ++i) racc += ext_weight_of<R>(i, I, X.sx, X.cnx, X.interp) * row[i];
+#pragma unroll
+        for (int a = 0; a < kMaxFoot; ++a)
+          if (ilo + a <= ihi) racc += wx[a] * row[a];
         acc += (wk * wj) * racc;
       }
     }

@@ -118,7 +118,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   }
   add((size_t)P->lv[0].n * 8);  // b
   const size_t nc = (size_t)P->lv[nl - 1].n;
-  add(nc * nc * 8); add(nc * nc * 8);  // A (then its factor), A^-1
+  add(nc * nc * 8); add(nc * nc * 8); add(nc * nc * 8);  // A (then its factor), row-major factor, A^-1
   add((size_t)kMaxPartials * 8);
   add(64);                                              // flags
   add(2 * MSCG_MAX_LEVELS * sizeof(long long));         // small-kernel counters
@@ -146,7 +146,7 @@ struct mscg_problem {
   int device;
   int nlev, ks;
   LevelH lev[MSCG_MAX_LEVELS];
-  double *Atmp, *Ainv;
+  double *Atmp, *Lrows, *Ainv;
   int ncoarse;
   double* part;
   double* b;
@@ -246,7 +246,9 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
     d.iters = P->dcount;
     d.calls = P->dcount + MSCG_MAX_LEVELS;
     d.status = P->dflags + 2;
-    HIP_TRY(launch_small_pcg<R>(d, P->stream));
+    const hipError_t e = launch_small_reg<R>(d, P->stream);
+    if (e == hipErrorNotSupported) HIP_TRY(launch_small_pcg<R>(d, P->stream));
+    else HIP_TRY(e);
     return MSCG_OK;
   }
   return pcg_host(P, kc);
@@ -394,6 +396,7 @@ int carve(mscg_problem* P, const Plan& plan) {
   P->b = (double*)take((size_t)plan.lv[0].n * 8);
   const size_t nc = (size_t)plan.lv[plan.nlev - 1].n;
   P->Atmp = (double*)take(nc * nc * 8);
+  P->Lrows = (double*)take(nc * nc * 8);
   P->Ainv = (double*)take(nc * nc * 8);
   P->ncoarse = (int)nc;
   P->part = (double*)take((size_t)kMaxPartials * 8);
@@ -575,7 +578,7 @@ int mscg_set_permeability(mscg_problem* P, const double* kx, const double* ky, c
     }
   }
   // coarsest factorisation
-  HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Ainv, P->dflags, P->stream));
+  HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Lrows, P->Ainv, P->dflags, P->stream));
   HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   if (P->hflags[0]) {

@@ -69,7 +69,8 @@ hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s);
 hipError_t launch_check_positive(const double* k, long long n, int* bad, hipStream_t s);
 hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s);
 hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
-hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Ainv, int* status, hipStream_t s);
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
+                                hipStream_t s);
 hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s);
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
 hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp, hipStream_t s);
@@ -104,6 +105,10 @@ template <typename R>
 hipError_t launch_copy(const R* a, R* b, long long n, hipStream_t s);
 template <typename R>
 hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s);
+// Register-resident variant for one small level directly above the coarsest
+// (at most 4096 cells); hipErrorNotSupported when the hierarchy does not fit.
+template <typename R>
+hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s);
 
 // Number of blocks (= partials) of a grid-wide reduction over n cells.
 inline int reduce_blocks(long long n) {

@@ -11,6 +11,9 @@ namespace mscg {
 namespace {
 
 constexpr int kBlock = 256;
+#define MSCG_COARSE_CAP 1024  // largest coarsest level (LDS of the inverse kernel)
+// dynamic LDS of the small-level solver: 160 KB per CU minus its static arrays
+constexpr size_t kSmallLdsBytes = 140 * 1024;
 
 inline int grid_for(long long n, int max_blocks = kMaxPartials) {
   long long b = (n + kBlock - 1) / kBlock;
@@ -204,45 +207,54 @@ __global__ void __launch_bounds__(1024) k_chol_factor(double* __restrict__ A, in
   if (tid == 0) status[0] = bad;
 }
 
-// A^-1 from the factor: thread c solves L L^T x = e_c (forward, then
-// backward substitution) and writes column c of A^-1 (= row c by symmetry)
-// into Ainv[k n + c].  The loops run from the wave's first column so every
-// lane reads the same L entry (a broadcast); entries above c are zero.
-__global__ void __launch_bounds__(kWave) k_chol_inverse(const double* __restrict__ L, double* __restrict__ Ainv, int n) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c0 = blockIdx.x * blockDim.x;
-  const bool on = c < n;
-  const int cc = on ? c : n - 1;
-  // forward: w = L^-1 e_c
-  for (int i = c0; i < n; ++i) {
-    double s0 = (i == cc) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = c0;
-    for (; k + 3 < i; k += 4) {
-      s0 -= L[(long long)k * n + i] * Ainv[(long long)k * n + cc];
-      s1 -= L[(long long)(k + 1) * n + i] * Ainv[(long long)(k + 1) * n + cc];
-      s2 -= L[(long long)(k + 2) * n + i] * Ainv[(long long)(k + 2) * n + cc];
-      s3 -= L[(long long)(k + 3) * n + i] * Ainv[(long long)(k + 3) * n + cc];
-    }
-    for (; k < i; ++k) s0 -= L[(long long)k * n + i] * Ainv[(long long)k * n + cc];
-    const double w = ((s0 + s1) + (s2 + s3)) / L[(long long)i * n + i];
-    if (on) Ainv[(long long)i * n + c] = i < c ? 0.0 : w;
+// Row-major copy of the lower factor: Lr[i n + k] = L[i][k] (k <= i).
+__global__ void k_factor_rows(const double* __restrict__ Lc, double* __restrict__ Lr, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), k = (int)(e % n);
+  Lr[e] = k <= i ? Lc[(long long)k * n + i] : 0.0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// A^-1 from the factor, one wave per column c: solve L w = e_c (forward),
+// then L^T x = w (backward); column c of A^-1 equals row c by symmetry and is
+// written to Ainv[c n + k].  The lanes split every row's dot product; lane l
+// owns the entries k = l (mod 64) of w and x, so each entry is written and
+// read by the same lane.  Forward rows read the row-major copy, backward rows
+// the column-major factor: both coalesced.
+__global__ void __launch_bounds__(256) k_chol_inverse(const double* __restrict__ Lc, const double* __restrict__ Lr,
+                                                      double* __restrict__ Ainv, int n) {
+  __shared__ double wbuf[4][MSCG_COARSE_CAP];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int c = blockIdx.x * 4 + wave;
+  if (c >= n) return;  // whole wave; no workgroup barrier in this kernel
+  double* w = wbuf[wave];
+  for (int k = lane; k < n; k += kWave) w[k] = 0.0;
+  // first owned index >= c for this lane
+  const int kc = c + ((lane - c % kWave) + kWave) % kWave;
+  for (int i = c; i < n; ++i) {
+    double part = 0.0;
+    for (int k = kc; k < i; k += kWave) part += Lr[(long long)i * n + k] * w[k];
+    part = wave_sum(part);
+    const double wi = ((i == c ? 1.0 : 0.0) - part) / Lr[(long long)i * n + i];
+    if ((i & (kWave - 1)) == lane) w[i] = wi;
   }
-  // backward: x = L^-T w
   for (int i = n - 1; i >= 0; --i) {
-    // rows above the wave's first column were not written by the forward
-    // pass: w is zero there
-    double s0 = i < c0 ? 0.0 : Ainv[(long long)i * n + cc], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = i + 1;
-    for (; k + 3 < n; k += 4) {
-      s0 -= L[(long long)i * n + k] * Ainv[(long long)k * n + cc];
-      s1 -= L[(long long)i * n + k + 1] * Ainv[(long long)(k + 1) * n + cc];
-      s2 -= L[(long long)i * n + k + 2] * Ainv[(long long)(k + 2) * n + cc];
-      s3 -= L[(long long)i * n + k + 3] * Ainv[(long long)(k + 3) * n + cc];
-    }
-    for (; k < n; ++k) s0 -= L[(long long)i * n + k] * Ainv[(long long)k * n + cc];
-    const double x = ((s0 + s1) + (s2 + s3)) / L[(long long)i * n + i];
-    if (on) Ainv[(long long)i * n + c] = x;
+    // owned indices k > i
+    const int k0 = i + 1 + ((lane - (i + 1) % kWave) + kWave) % kWave;
+    double part = 0.0;
+    for (int k = k0; k < n; k += kWave) part += Lc[(long long)i * n + k] * w[k];
+    part = wave_sum(part);
+    const double wi = (i & (kWave - 1)) == lane ? w[i] : 0.0;
+    const double wval = wave_sum(wi);  // broadcast w_i from its owner
+    const double xi = (wval - part) / Lc[(long long)i * n + i];
+    if ((i & (kWave - 1)) == lane) w[i] = xi;
   }
+  for (int k = lane; k < n; k += kWave) Ainv[(long long)c * n + k] = w[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -466,8 +478,9 @@ template <typename R>
 struct SmallLevel {
   Lv<R> L;
   Xfer X;                 // to level + 1
-  R *x, *r, *z, *p, *q;   // q may alias nothing
+  R *x, *r, *z, *p, *q;
   double tol;             // absolute criterion on |r|^2
+  int lds_T, lds_z, lds_r, lds_x;  // byte offsets into dynamic LDS, -1 = stays in global memory
 };
 
 template <typename R>
@@ -484,21 +497,59 @@ struct SmallArgs {
 };
 
 template <typename R>
-__global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
+__global__ void __launch_bounds__(1024, 1) k_small_pcg(SmallArgs<R> args) {
   __shared__ double sm[1024 / kWave];
   __shared__ double sh_rho[kMaxLevels], sh_rr[kMaxLevels], sh_tol[kMaxLevels];
   __shared__ int sh_it[kMaxLevels];
   __shared__ double sh_g[1024], sh_part[1024];
+  __shared__ SmallLevel<R> lv[kMaxLevels];  // level descriptors, LDS-resident for dynamic indexing
+  __shared__ long long my_iters[kMaxLevels], my_calls[kMaxLevels];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
+  const SmallArgs<R>& a = args;
   const int L = a.nlev - 1;  // coarsest index
-  long long my_iters[kMaxLevels], my_calls[kMaxLevels];
-  for (int l = 0; l < kMaxLevels; ++l) { my_iters[l] = 0; my_calls[l] = 0; }
+  if (tid < kMaxLevels) {
+    lv[tid] = a.lv[tid];
+    my_iters[tid] = 0;
+    my_calls[tid] = 0;
+  }
+  __syncthreads();
+
+  // Stage the face transmissibilities and the smoother's vectors of the
+  // levels that fit into LDS: the 2(2m+1) half sweeps per iteration then read
+  // LDS instead of L2.  The rhs of level ks arrives in global memory; x of
+  // level ks is the result and stays there.
+  for (int l = a.ks; l <= L; ++l) {
+    const SmallLevel<R>& S = a.lv[l];
+    if (S.lds_T >= 0) {
+      R* t = reinterpret_cast<R*>(dyn_lds + S.lds_T);
+      const int fx = (S.L.nx + 1) * S.L.ny * S.L.nz, fy = S.L.nx * (S.L.ny + 1) * S.L.nz;
+      const int fz = S.L.tz ? S.L.nx * S.L.ny * (S.L.nz + 1) : 0;
+      for (int e = tid; e < fx; e += nt) t[e] = S.L.tx[e];
+      for (int e = tid; e < fy; e += nt) t[fx + e] = S.L.ty[e];
+      for (int e = tid; e < fz; e += nt) t[fx + fy + e] = S.L.tz[e];
+      if (tid == 0) {
+        lv[l].L.tx = t;
+        lv[l].L.ty = t + fx;
+        if (fz) lv[l].L.tz = t + fx + fy;
+      }
+    }
+    if (S.lds_z >= 0 && tid == 0) lv[l].z = reinterpret_cast<R*>(dyn_lds + S.lds_z);
+    if (S.lds_r >= 0) {
+      R* rr = reinterpret_cast<R*>(dyn_lds + S.lds_r);
+      if (l == a.ks)
+        for (int c = tid; c < S.L.n; c += nt) rr[c] = S.r[c];
+      if (tid == 0) lv[l].r = rr;
+    }
+    if (S.lds_x >= 0 && l > a.ks && tid == 0) lv[l].x = reinterpret_cast<R*>(dyn_lds + S.lds_x);
+  }
+  __syncthreads();
   int status = 0;
 
   // start the PCG of level k: x = 0, r already holds the rhs.  Returns true if
   // the entry check is already satisfied.
   auto start = [&](int k) -> bool {
-    SmallLevel<R>& S = a.lv[k];
+    SmallLevel<R>& S = lv[k];
     for (int c = tid; c < S.L.n; c += nt) S.x[c] = R(0);
     double acc = 0.0;
     for (int c = tid; c < S.L.n; c += nt) acc += (double)S.r[c] * (double)S.r[c];
@@ -506,14 +557,14 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
     double tol = S.tol;
     if (a.rel_floor2 > 0.0 && a.rel_floor2 * rr > tol) tol = a.rel_floor2 * rr;
     if (tid == 0) { sh_rr[k] = rr; sh_tol[k] = tol; sh_it[k] = 0; }
-    my_calls[k] += 1;
+    if (tid == 0) my_calls[k] += 1;
     __syncthreads();
     return rr < tol;
   };
   // pre-smoothing of level k from x = 0 (m SGS steps = R,B,R,...,R: 2m+1 half
   // sweeps, repeated colours being idempotent) and g_{k+1} = E^T (r - A z).
   auto pre = [&](int k) {
-    SmallLevel<R>& S = a.lv[k];
+    SmallLevel<R>& S = lv[k];
     for (int h = 0; h <= 2 * a.m; ++h) {
       gs_half_range(S.L, S.r, S.z, h & 1, h == 0, tid, nt);
       __syncthreads();
@@ -527,13 +578,13 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
       S.q[c] = S.r[c] - (d * S.z[c] - o);
     }
     __syncthreads();
-    restrict_stored_range(S.L, S.X, (const R*)S.q, a.lv[k + 1].r, tid, nt);
+    restrict_stored_range(S.L, S.X, (const R*)S.q, lv[k + 1].r, tid, nt);
     __syncthreads();
   };
   // y = A^-1 g on the coarsest level: the columns of A^-1 are split into
   // nt / nc groups whose partial sums are added in group order.
   auto coarse = [&]() {
-    SmallLevel<R>& C = a.lv[L];
+    SmallLevel<R>& C = lv[L];
     const int nc = a.ncoarse;
     for (int i = tid; i < nc; i += nt) sh_g[i] = (double)C.r[i];
     __syncthreads();
@@ -554,13 +605,13 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
       for (int grp = 0; grp < groups; ++grp) s += sh_part[grp * nc + i];
       C.x[i] = (R)s;
     }
-    my_calls[L] += 1;
+    if (tid == 0) my_calls[L] += 1;
     __syncthreads();
   };
   // post-smoothing of level k and one CG step; returns true when level k is done
   auto post_step = [&](int k) -> bool {
-    SmallLevel<R>& S = a.lv[k];
-    prolong_range(S.L, S.X, a.lv[k + 1].x, S.z, tid, nt);
+    SmallLevel<R>& S = lv[k];
+    prolong_range(S.L, S.X, lv[k + 1].x, S.z, tid, nt);
     __syncthreads();
     for (int h = 0; h <= 2 * a.m; ++h) {
       gs_half_range(S.L, S.r, S.z, h & 1, false, tid, nt);
@@ -586,8 +637,7 @@ __global__ void __launch_bounds__(1024) k_small_pcg(SmallArgs<R> a) {
       acc += (double)v * (double)v;
     }
     const double rr = block_sum(acc, sm);
-    if (tid == 0) { sh_rho[k] = rho; sh_rr[k] = rr; sh_it[k] = it + 1; }
-    my_iters[k] += 1;
+    if (tid == 0) { sh_rho[k] = rho; sh_rr[k] = rr; sh_it[k] = it + 1; my_iters[k] += 1; }
     __syncthreads();
     return rr < sh_tol[k] || it + 1 >= a.max_inner;
   };
@@ -654,10 +704,14 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Ainv, int* status, hipStream_t s) {
+hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
+                                hipStream_t s) {
+  if (L.n > MSCG_COARSE_CAP) return hipErrorInvalidValue;
+  const long long nn = (long long)L.n * L.n;
   hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
   hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, A, L.n, status);
-  hipLaunchKernelGGL(k_chol_inverse, dim3((L.n + kWave - 1) / kWave), dim3(kWave), 0, s, A, Ainv, L.n);
+  hipLaunchKernelGGL(k_factor_rows, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, Lrows, L.n);
+  hipLaunchKernelGGL(k_chol_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, A, Lrows, Ainv, L.n);
   return hipGetLastError();
 }
 
@@ -711,8 +765,12 @@ hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, c
                                     hipStream_t s) {
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
   hipLaunchKernelGGL(k_residual_nodot<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, r, x, tmp);
-  hipLaunchKernelGGL(k_restrict_stored<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X,
-                     (const R*)tmp, g);
+  // one thread per coarse cell; small coarse grids use 64-thread blocks to spread over more CUs
+  if (nc < 65536)
+    hipLaunchKernelGGL(k_restrict_stored<R>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, F, X, (const R*)tmp, g);
+  else
+    hipLaunchKernelGGL(k_restrict_stored<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X,
+                       (const R*)tmp, g);
   return hipGetLastError();
 }
 
@@ -789,7 +847,36 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
   a.iters = d.iters;
   a.calls = d.calls;
   a.status = d.status;
-  hipLaunchKernelGGL(k_small_pcg<R>, dim3(1), dim3(1024), 0, s, a);
+  // LDS plan: per level from the top small level down, faces then z then r;
+  // then the coarsest level's rhs and solution; each array only if it fits.
+  size_t off = 0;
+  auto fit = [&](size_t bytes) -> int {
+    bytes = (bytes + 15) & ~(size_t)15;
+    if (off + bytes > kSmallLdsBytes) return -1;
+    const int o = (int)off;
+    off += bytes;
+    return o;
+  };
+  for (int l = 0; l < kMaxLevels; ++l) a.lv[l].lds_T = a.lv[l].lds_z = a.lv[l].lds_r = a.lv[l].lds_x = -1;
+  const int Lc = d.nlev - 1;
+  for (int l = d.ks; l < Lc; ++l) {
+    const Lv<R>& V = d.L[l];
+    const size_t faces = (size_t)(V.nx + 1) * V.ny * V.nz + (size_t)V.nx * (V.ny + 1) * V.nz +
+                         (V.tz ? (size_t)V.nx * V.ny * (V.nz + 1) : 0);
+    a.lv[l].lds_T = fit(faces * sizeof(R));
+    a.lv[l].lds_z = fit((size_t)V.n * sizeof(R));
+    a.lv[l].lds_r = fit((size_t)V.n * sizeof(R));
+  }
+  a.lv[Lc].lds_r = fit((size_t)d.L[Lc].n * sizeof(R));
+  a.lv[Lc].lds_x = fit((size_t)d.L[Lc].n * sizeof(R));
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_small_pcg<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kSmallLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_small_pcg<R>, dim3(1), dim3(1024), off, s, a);
   return hipGetLastError();
 }
 
