@@ -81,7 +81,8 @@ typedef struct {
   int max_outer_iters;    /* default 200 */
   int max_inner_iters;    /* per inner PCG call, default 200 */
   int interp;             /* MSCG_INTERP_LINEAR (default) or MSCG_INTERP_CONSTANT */
-  int flexible;           /* 0: Fletcher-Reeves beta (Templates CG, default); 1: Polak-Ribiere */
+  int flexible;           /* beta on the host-driven levels: 0 Fletcher-Reeves (Templates CG, default),
+                             1 Polak-Ribiere, robust to a preconditioner that varies between iterations */
   double inner_rel_floor; /* MIXED only: inner levels stop once |r| <= floor * |rhs| (default 1e-6) */
 } mscg_options;
 

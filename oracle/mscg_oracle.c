@@ -459,7 +459,10 @@ static int pcg_level(or_problem *P, int k, const double *b, double *x, int x_is_
   for (it = 1; it <= max_iter; ++it) {
     precond(P, k, r, z);
     double rho = dot(n, r, z);
-    if (!(rho > 0.0)) { P->status = -4; break; }
+    /* r.z <= 0 (or p.Ap <= 0): no further progress in finite precision.  An
+     * inner level stops there (its solve is approximate by design); on the
+     * finest level, or with a non-finite value, it is a breakdown. */
+    if (!(rho > 0.0)) { if (k == 0 || rho != rho) P->status = -4; break; }
     if (it == 1) memcpy(p, z, sizeof(double) * n);
     else {
       double beta = rho / rho_old;
@@ -467,7 +470,7 @@ static int pcg_level(or_problem *P, int k, const double *b, double *x, int x_is_
     }
     apply_A(L, p, q);
     double pq = dot(n, p, q);
-    if (!(pq > 0.0)) { P->status = -4; break; }
+    if (!(pq > 0.0)) { if (k == 0 || pq != pq) P->status = -4; break; }
     double alpha = rho / pq;
     for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
     for (int i = 0; i < n; ++i) r[i] -= alpha * q[i];

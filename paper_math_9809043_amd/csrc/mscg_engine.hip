@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -197,8 +198,10 @@ int read_scal(mscg_problem* P, int k) {
 // Device scalars live in the caller's workspace, whose contents are arbitrary.
 int clear_scalars(mscg_problem* P) {
   static_assert(sizeof(Scal) % sizeof(double) == 0, "Scal is cleared as doubles");
-  for (int l = 0; l < P->nlev; ++l)
+  for (int l = 0; l < P->nlev; ++l) {
     HIP_TRY(launch_fill<double>(reinterpret_cast<double*>(P->lev[l].sc), sizeof(Scal) / sizeof(double), 0.0, P->stream));
+    if (P->o.flexible) HIP_TRY(launch_fill<int>(&P->lev[l].sc->flexible, 1, 1, P->stream));
+  }
   return MSCG_OK;
 }
 
@@ -311,6 +314,10 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* q
   for (int it = 0; it < max_iter; ++it) {
     int rc = apply_prec(P, k);
     if (rc) return rc;
+    if (P->o.flexible && it > 0) {
+      HIP_TRY(launch_dot<R>(z, q, L.n, P->part, nb, P->stream));
+      HIP_TRY(launch_finish(P->part, nb, H.sc, kOpZq, P->stream));
+    }
     HIP_TRY(launch_dot<R>(r, z, L.n, P->part, nb, P->stream));
     HIP_TRY(launch_finish(P->part, nb, H.sc, kOpRho, P->stream));
     HIP_TRY(launch_update_p<R>(z, p, L.n, H.sc, P->stream));
@@ -321,8 +328,15 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* q
     P->iters[k]++;
     rc = read_scal(P, k);
     if (rc) return rc;
-    if (P->hsc->status) { P->status = MSCG_E_BREAKDOWN; return MSCG_OK; }
-    if (P->hsc->converged) break;
+    // a stall (r.z or p.Ap <= 0 in finite precision) ends an inner level
+    // quietly; on the finest level, and for non-finite values, it is a breakdown
+    if (P->hsc->status < 0 || (P->hsc->status > 0 && k == 0)) {
+      P->status = MSCG_E_BREAKDOWN;
+      fail(MSCG_E_BREAKDOWN, "level %d iteration %d: %s (rho %g, alpha %g, rr %g)", k, it + 1,
+           P->hsc->status < 0 ? "non-finite reduction" : "r.z or p.Ap <= 0", P->hsc->rho, P->hsc->alpha, P->hsc->rr);
+      return MSCG_OK;
+    }
+    if (P->hsc->status > 0 || P->hsc->converged) break;
     if (k == 0 && mixed(P)) P->tol_scale = P->hsc->rr > 0.0 ? 1.0 / P->hsc->rr : 1.0;
   }
   return MSCG_OK;
@@ -652,7 +666,10 @@ static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_to
   const double rt = P->hsc->bb;
   auto t1 = std::chrono::steady_clock::now();
   int status = P->status;
-  if (P->hflags[2]) status = MSCG_E_BREAKDOWN;
+  if (P->hflags[2]) {
+    status = MSCG_E_BREAKDOWN;
+    fail(MSCG_E_BREAKDOWN, "non-finite reduction in the one-workgroup inner solver (level >= %d)", P->ks);
+  }
   const bool converged_rec = P->nlev == 1 || P->hsc->converged;
   if (status == MSCG_OK && !converged_rec) status = MSCG_NOT_CONVERGED;
   if (st) {
@@ -686,10 +703,30 @@ int mscg_solve_batch(mscg_problem* const* probs, const double* const* f, double*
                      int count, mscg_stats* stats) {
   g_err.clear();
   if (count < 0 || (count > 0 && (!probs || !f || !p || !rel_tol))) return fail(MSCG_E_ARG, "bad batch arguments");
+  for (int i = 0; i < count; ++i) {
+    if (!probs[i]) return fail(MSCG_E_ARG, "probs[%d] is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i]) return fail(MSCG_E_ARG, "probs[%d] and probs[%d] are the same problem", j, i);
+  }
+  // one host thread per problem: each drives its problem's own stream, so the
+  // solves' kernels overlap on the device
+  std::vector<int> rcs(count, MSCG_OK);
+  std::vector<std::string> errs(count);
+  std::vector<std::thread> th;
+  th.reserve(count);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (int i = 0; i < count; ++i)
+    th.emplace_back([&, i]() {
+      (void)hipSetDevice(dev);
+      rcs[i] = mscg_solve(probs[i], f[i], p[i], rel_tol[i], 0, stats ? &stats[i] : nullptr);
+      if (rcs[i] < 0) errs[i] = g_err;
+    });
+  for (auto& t : th) t.join();
   int worst = MSCG_OK;
   for (int i = 0; i < count; ++i) {
-    const int rc = mscg_solve(probs[i], f[i], p[i], rel_tol[i], 0, stats ? &stats[i] : nullptr);
-    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+    const int rc = rcs[i];
+    if (rc < 0 && (worst >= 0 || rc < worst)) { worst = rc; g_err = errs[i]; }
     else if (rc > 0 && worst == MSCG_OK) worst = rc;
   }
   return worst;

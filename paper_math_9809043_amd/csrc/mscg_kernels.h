@@ -18,13 +18,14 @@ struct Scal {
   double beta;  // rho / rho_previous
   double alpha; // rho / (p . A p)
   double tol;   // absolute criterion on |r|^2: N_k f^k eps^2
+  double zq;    // z_new . q_old (flexible beta)
   int it;       // iterations done in the current call
   int converged;
   int status;   // 0 or -4 (breakdown)
-  int pad;
+  int flexible; // beta: 0 Fletcher-Reeves rho/rho_old, 1 Polak-Ribiere z.(r - r_old)/rho_old
 };
 
-enum { kOpBB = 0, kOpEntry = 1, kOpRho = 2, kOpPq = 3, kOpRr = 4 };
+enum { kOpBB = 0, kOpEntry = 1, kOpRho = 2, kOpPq = 3, kOpRr = 4, kOpZq = 5 };
 
 struct FaceTArgs {
   int dim, nx, ny, nz;

@@ -397,12 +397,20 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ pa
       if (!(s == s) || s == INFINITY) sc->status = -4;
       break;
     case kOpRho:
-      if (!(s > 0.0) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
-      sc->beta = sc->it == 0 ? 0.0 : s / sc->rho;
+      // r.z <= 0 in finite precision: no further progress (status 1, the
+      // caller decides); a non-finite value is a breakdown (-4)
+      if (!(s == s) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
+      else if (!(s > 0.0)) { sc->status = 1; sc->converged = 1; }
+      // r_new - r_old = -alpha q_old, so z.(r_new - r_old) = -alpha (z.q_old)
+      sc->beta = sc->it == 0 ? 0.0 : (sc->flexible ? -sc->alpha * sc->zq / sc->rho : s / sc->rho);
       sc->rho = s;
       break;
+    case kOpZq:
+      sc->zq = s;
+      break;
     case kOpPq:
-      if (!(s > 0.0) || s == INFINITY) { sc->status = -4; sc->converged = 1; sc->alpha = 0.0; }
+      if (!(s == s) || s == INFINITY) { sc->status = -4; sc->converged = 1; sc->alpha = 0.0; }
+      else if (!(s > 0.0) || sc->status != 0) { if (sc->status == 0) sc->status = 1; sc->converged = 1; sc->alpha = 0.0; }
       else sc->alpha = sc->rho / s;
       break;
     case kOpRr:
@@ -622,12 +630,14 @@ __global__ void __launch_bounds__(1024, 1) k_small_pcg(SmallArgs<R> args) {
     for (int c = tid; c < S.L.n; c += nt) acc += (double)S.r[c] * (double)S.z[c];
     const double rho = block_sum(acc, sm);
     const int it = sh_it[k];
-    if (!(rho > 0.0)) { status = -4; return true; }
+    if (!(rho == rho) || rho == INFINITY) { status = -4; return true; }
+    if (!(rho > 0.0)) return true;  // no further progress in this precision: the level stops
     const R beta = it == 0 ? R(0) : (R)(rho / sh_rho[k]);
     for (int c = tid; c < S.L.n; c += nt) S.p[c] = it == 0 ? S.z[c] : S.z[c] + beta * S.p[c];
     __syncthreads();
     const double pq = block_sum(spmv_range<R, double>(S.L, S.p, S.q, tid, nt), sm);
-    if (!(pq > 0.0)) { status = -4; return true; }
+    if (!(pq == pq) || pq == INFINITY) { status = -4; return true; }
+    if (!(pq > 0.0)) return true;
     const R alpha = (R)(rho / pq);
     acc = 0.0;
     for (int c = tid; c < S.L.n; c += nt) {

@@ -172,3 +172,32 @@ def request_stream(count: int = 4096, rate_per_s: float = 1000.0, sides=(64, 128
 def request_problem(req: Request, tol: float = 1e-8) -> Problem:
     """The serving stream's field: smoothed log-normal with log10 k ~ U[-3, 3] (contrast 1e6)."""
     return smoothed_lognormal_2d(req.seed, req.side, lo=-3.0, hi=3.0, tol=tol, name=f"req{req.idx}_{req.side}")
+
+
+def request_fields_torch(req: Request, device, lo: float = -3.0, hi: float = 3.0, stream=None):
+    """The serving stream's request drawn on the GPU from the request's seed.
+
+    Same recipe as `smoothed_lognormal_2d` (log10 k ~ U[lo, hi] i.i.d., 3x3
+    box mean with the window truncated at the edges, f ~ N(0, 1)), drawn by a
+    seeded torch generator on `device` so a request's inputs appear in HBM
+    without a host round trip.  Returns (k, f) as flat float64 device tensors.
+    """
+    import torch
+    import torch.nn.functional as F
+    n = req.side
+    g = torch.Generator(device=device)
+    g.manual_seed(req.seed)
+    with torch.cuda.stream(stream) if stream is not None else _null():
+        u = torch.rand((1, 1, n, n), generator=g, device=device, dtype=torch.float64) * (hi - lo) + lo
+        f = torch.randn((n * n,), generator=g, device=device, dtype=torch.float64)
+        logk = F.avg_pool2d(u, 3, stride=1, padding=1, count_include_pad=False)
+        k = torch.pow(10.0, logk).reshape(-1).contiguous()
+    return k, f
+
+
+class _null:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
