@@ -81,6 +81,30 @@ def run_gpu(P, opt, steps, warmup):
     return prob, st, wall_ms, solve_ms, p
 
 
+def run_serving(count):
+    """Serving stream: sides U{64,128,256,512}, contrast 1e6, tol 1e-8, mixed precision.
+    Saturation throughput from a burst, then Poisson arrivals at 0.7x that rate."""
+    from paper_math_9809043_amd import mscg, serve, synth
+    opts = mscg.Options(precision=mscg.MIXED)
+    srv = serve.Server(slots=8, budget_bytes=16 << 30, options=opts, tol=1e-8)
+    warm = [synth.Request(i, 0.0, side, 10 + i) for i, side in enumerate((64, 128, 256, 512) * 8)]
+    srv.run(warm)  # creates every slot's resident hierarchies
+    burst = synth.request_stream(min(512, count), rate_per_s=1e9, arrival_seed=11, first_seed=50000)
+    sat = srv.run(burst).summary()["solves_per_s"]
+    rate = 0.7 * sat
+    reqs = synth.request_stream(count, rate_per_s=rate, arrival_seed=7, first_seed=1000)
+    print(f"[bench] serving: saturation {sat:.1f} solves/s, replaying {count} requests at {rate:.1f}/s", flush=True)
+    rep = srv.run(reqs)
+    s = rep.summary()
+    s.update({"arrival_rate_per_s": round(rate, 2), "saturation_solves_per_s": sat, "slots": srv.nslots,
+              "budget_bytes": srv.budget, "precision": "mixed", "tol": 1e-8,
+              "workload": f"{count} 2-D requests, side ~ U{{64,128,256,512}}, smoothed log-normal contrast 1e6, "
+                          "Poisson arrivals"})
+    print(f"[bench] serving: {s['solves_per_s']} solves/s p50 {s['p50_ms']} ms p99 {s['p99_ms']} ms "
+          f"ok {s['ok']}/{s['requests']}", flush=True)
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +113,9 @@ def main():
     ap.add_argument("--workload", default="smooth1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one process, one MI355X).",
@@ -142,6 +169,26 @@ def main():
         cpu["gpu_rel_err_vs_oracle"] = float(np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p))
         print(f"[bench] oracle: {t1 - t0:.2f} s", flush=True)
 
+    serving = None
+    if not args.no_serve:
+        serving = run_serving(args.serve_requests)
+
+    extra = {}
+    if not args.no_3d and args.workload != "layered128":
+        W3 = WORKLOADS["layered128"]
+        P3 = make_problem(W3["make"])
+        _, st3, wall3, solve3, _ = run_gpu(P3, W3["opt"], 2, 1)
+        opt3 = dict(W3["opt"])
+        opt3["precision"] = mscg.MIXED
+        _, st3m, wall3m, solve3m, _ = run_gpu(P3, opt3, 2, 1)
+        extra["layered128"] = {"workload": W3["desc"], "fp64": {"value": round(P3.N / (wall3 * 1e-3), 1),
+                               "ms_per_step": round(wall3, 3), "outer_iters": st3.outer_iters,
+                               "level_iters": st3.level_iters, "rel_residual_true": st3.rel_residual_true},
+                               "mixed": {"value": round(P3.N / (wall3m * 1e-3), 1), "ms_per_step": round(wall3m, 3),
+                                         "outer_iters": st3m.outer_iters,
+                                         "rel_residual_true": st3m.rel_residual_true}}
+        print(f"[bench] layered128: fp64 {wall3:.1f} ms, mixed {wall3m:.1f} ms", flush=True)
+
     value = P.N / (wall_ms * 1e-3)
     line = {
         "metric": "unknowns solved/s to 1e-10 resid (set-up + solve), FP64 plain method; mixed alongside",
@@ -154,6 +201,8 @@ def main():
         "mixed": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "extra_workloads": extra,
     }
     print(json.dumps(line), flush=True)
 
