@@ -113,8 +113,8 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
     add(fx * 8); add(fy * 8); if (fz) add(fz * 8);
     if (mixed) { add(fx * 4); add(fy * 4); if (fz) add(fz * 4); }
     const bool fp64_vec = !mixed || l == 0;
-    for (int v = 0; v < 5; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
-    if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, iterate, residual
+    for (int v = 0; v < 6; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
+    if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, iterate, output
     add(sizeof(Scal));
   }
   add((size_t)P->lv[0].n * 8);  // b
@@ -133,8 +133,8 @@ struct LevelH {
   int sx, sy, sz;
   double *tx, *ty, *tz;
   float *tx32, *ty32, *tz32;
-  double *x, *r, *z, *p, *q;  // FP64 vectors (FP64 mode, or level 0)
-  float *x32, *r32, *z32, *p32, *q32;  // FP32 vectors (mixed inner levels; level 0: r32 = scaled r, z32 = iterate)
+  double *x, *r, *z, *p, *q, *w;  // FP64 vectors (FP64 mode, or level 0); w: residual / post-smoothing output
+  float *x32, *r32, *z32, *p32, *q32, *w32;  // FP32 vectors (mixed inner levels; level 0: r32, z32, w32)
   Scal* sc;
 };
 
@@ -160,6 +160,7 @@ struct mscg_problem {
   size_t ws_bytes;
   bool owns_ws;
   bool ready;
+  bool tiled;         // 2-D levels smooth with the tiled kernel
   // per-solve state
   double eps2;
   double tol_scale;   // mixed: 1 / |r|^2 of the current outer iteration
@@ -257,18 +258,39 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
   return pcg_host(P, kc);
 }
 
-// z_k = M_k^-1 r_k (eq. 2.10 as a two-grid cycle).  Vectors of type R.
+// z_k = M_k^-1 r_k (eq. 2.10 as a two-grid cycle).  Vectors of type R.  The
+// pre-smoothing iterate is z; w holds the residual for the restriction and
+// then, on 2-D levels, the output of the tiled post-smoothing (which cannot
+// run in place: its halos read neighbouring tiles).  Returns the vector that
+// holds M_k^-1 r_k.  q is not touched, so the flexible beta can still use it.
 template <typename R>
-int precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* const* xs, R* const* rs, R* const* zs,
-                 R* const* ps, R* const* qs) {
+R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, R* const* xs, R* const* rs,
+                R* const* zs, R* const* ps, R* const* qs, int* rc) {
   const int m = P->o.smooth_steps;
-  for (int h = 0; h <= 2 * m; ++h) HIP_TRY(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream));
-  HIP_TRY(launch_residual_restrict<R>(L, xfer(P, k), r, z, qs[k], rs[k + 1], P->stream));
-  int rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
-  if (rc) return rc;
-  HIP_TRY(launch_prolong<R>(L, xfer(P, k), xs[k + 1], z, P->stream));
-  for (int h = 0; h <= 2 * m; ++h) HIP_TRY(launch_gs_half<R>(L, r, z, h & 1, 0, P->stream));
-  return MSCG_OK;
+  const Xfer X = xfer(P, k);
+  *rc = MSCG_OK;
+  auto chk = [&](hipError_t e) {
+    if (e != hipSuccess && *rc == MSCG_OK) *rc = fail(MSCG_E_DEVICE, "precond level %d: %s", k, hipGetErrorString(e));
+    return e == hipSuccess;
+  };
+  const bool tiled = P->tiled && L.nz == 1;
+  if (tiled) {
+    if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->stream))) return nullptr;
+  } else {
+    for (int h = 0; h <= 2 * m; ++h)
+      if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream))) return nullptr;
+  }
+  if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream))) return nullptr;
+  *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
+  if (*rc) return nullptr;
+  if (tiled) {
+    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->stream))) return nullptr;
+    return w;
+  }
+  if (!chk(launch_prolong<R>(L, X, xs[k + 1], z, P->stream))) return nullptr;
+  for (int h = 0; h <= 2 * m; ++h)
+    if (!chk(launch_gs_half<R>(L, r, z, h & 1, 0, P->stream))) return nullptr;
+  return z;
 }
 
 template <typename R>
@@ -283,12 +305,16 @@ void vec_tables(mscg_problem* P, R** xs, R** rs, R** zs, R** ps, R** qs) {
   }
 }
 
-// Applies the level-k preconditioner to the level's residual into z_k.
-int apply_prec(mscg_problem* P, int k) {
+// Applies the level-k preconditioner to the level's residual; *out receives
+// the vector (in the level's CG precision) that holds the result.
+int apply_prec(mscg_problem* P, int k, void** out) {
+  int rc = MSCG_OK;
   if (!mixed(P)) {
     double *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
     vec_tables<double>(P, xs, rs, zs, ps, qs);
-    return precond_host<double>(P, k, lv64(P, k), P->lev[k].r, P->lev[k].z, xs, rs, zs, ps, qs);
+    LevelH& H = P->lev[k];
+    *out = precond_host<double>(P, k, lv64(P, k), H.r, H.z, H.w, xs, rs, zs, ps, qs, &rc);
+    return rc;
   }
   float *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
   vec_tables<float>(P, xs, rs, zs, ps, qs);
@@ -297,12 +323,15 @@ int apply_prec(mscg_problem* P, int k) {
     // the inner solves only need the overall accuracy; the outer CG recovers FP64)
     LevelH& L0 = P->lev[0];
     HIP_TRY(launch_scale_to_f32(L0.r, L0.r32, L0.n, L0.sc, P->stream));
-    int rc = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, xs, rs, zs, ps, qs);
+    float* z32 = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc);
     if (rc) return rc;
-    HIP_TRY(launch_scale_to_f64(L0.z32, L0.z, L0.n, L0.sc, P->stream));
+    HIP_TRY(launch_scale_to_f64(z32, L0.z, L0.n, L0.sc, P->stream));
+    *out = L0.z;
     return MSCG_OK;
   }
-  return precond_host<float>(P, k, lv32(P, k), P->lev[k].r32, P->lev[k].z32, xs, rs, zs, ps, qs);
+  LevelH& H = P->lev[k];
+  *out = precond_host<float>(P, k, lv32(P, k), H.r32, H.z32, H.w32, xs, rs, zs, ps, qs, &rc);
+  return rc;
 }
 
 // One level's CG loop (Templates Figure 2.5) on vectors of type R; the residual
@@ -312,8 +341,10 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* q
   LevelH& H = P->lev[k];
   const int nb = reduce_blocks(L.n);
   for (int it = 0; it < max_iter; ++it) {
-    int rc = apply_prec(P, k);
+    void* zres = nullptr;
+    int rc = apply_prec(P, k, &zres);
     if (rc) return rc;
+    z = static_cast<R*>(zres);
     if (P->o.flexible && it > 0) {
       HIP_TRY(launch_dot<R>(z, q, L.n, P->part, nb, P->stream));
       HIP_TRY(launch_finish(P->part, nb, H.sc, kOpZq, P->stream));
@@ -391,19 +422,19 @@ int carve(mscg_problem* P, const Plan& plan) {
     L.tx = (double*)take(fx * 8); L.ty = (double*)take(fy * 8); L.tz = fz ? (double*)take(fz * 8) : nullptr;
     L.tx32 = L.ty32 = L.tz32 = nullptr;
     if (mx) { L.tx32 = (float*)take(fx * 4); L.ty32 = (float*)take(fy * 4); L.tz32 = fz ? (float*)take(fz * 4) : nullptr; }
-    L.x = L.r = L.z = L.p = L.q = nullptr;
-    L.x32 = L.r32 = L.z32 = L.p32 = L.q32 = nullptr;
+    L.x = L.r = L.z = L.p = L.q = L.w = nullptr;
+    L.x32 = L.r32 = L.z32 = L.p32 = L.q32 = L.w32 = nullptr;
     if (!mx || l == 0) {
       L.x = (double*)take((size_t)L.n * 8); L.r = (double*)take((size_t)L.n * 8); L.z = (double*)take((size_t)L.n * 8);
-      L.p = (double*)take((size_t)L.n * 8); L.q = (double*)take((size_t)L.n * 8);
+      L.p = (double*)take((size_t)L.n * 8); L.q = (double*)take((size_t)L.n * 8); L.w = (double*)take((size_t)L.n * 8);
     } else {
       L.x32 = (float*)take((size_t)L.n * 4); L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4);
-      L.p32 = (float*)take((size_t)L.n * 4); L.q32 = (float*)take((size_t)L.n * 4);
+      L.p32 = (float*)take((size_t)L.n * 4); L.q32 = (float*)take((size_t)L.n * 4); L.w32 = (float*)take((size_t)L.n * 4);
     }
     if (mx && l == 0) {
       L.r32 = (float*)take((size_t)L.n * 4);
       L.z32 = (float*)take((size_t)L.n * 4);
-      L.q32 = (float*)take((size_t)L.n * 4);
+      L.w32 = (float*)take((size_t)L.n * 4);
     }
     L.sc = (Scal*)take(sizeof(Scal));
   }
@@ -524,6 +555,10 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
     }
   }
   P->ready = false;
+  {
+    const char* e = getenv("MSCG_UNTILED");
+    P->tiled = !(e && e[0] == '1');
+  }
   *out = P;
   return MSCG_OK;
 }
@@ -810,9 +845,10 @@ int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, doubl
   HIP_TRY(launch_fill<long long>(P->dcount, 2 * MSCG_MAX_LEVELS, 0, P->stream));
   int rc = clear_scalars(P);
   if (rc) return rc;
-  rc = apply_prec(P, 0);
+  void* zres = nullptr;
+  rc = apply_prec(P, 0, &zres);
   if (rc) return rc;
-  HIP_TRY(launch_copy<double>(L0.z, z, L0.n, P->stream));
+  HIP_TRY(launch_copy<double>(static_cast<const double*>(zres), z, L0.n, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return P->status;
 }

@@ -111,6 +111,14 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s);
 template <typename R>
 hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s);
 
+// m symmetric Gauss-Seidel steps (2m+1 red-black half sweeps) on a 2-D level,
+// temporally blocked in LDS.  X == nullptr: pre-smoothing from zero into zout;
+// otherwise post-smoothing from zin + E y into zout (zout must not alias zin).
+// hipErrorNotSupported for 3-D levels or when the tile does not fit LDS.
+template <typename R>
+hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, int m,
+                              hipStream_t s);
+
 // Number of blocks (= partials) of a grid-wide reduction over n cells.
 inline int reduce_blocks(long long n) {
   long long b = (n + 255) / 256;
