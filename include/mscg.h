@@ -182,7 +182,9 @@ enum {
   MSCG_KERNEL_SPMV = 1,        /* q = A p with the partial sums of p.q */
   MSCG_KERNEL_RESTRICT = 2,    /* g = R (r - A x) */
   MSCG_KERNEL_PROLONG = 3,     /* x += E y */
-  MSCG_KERNEL_CG_UPDATE = 4    /* x += alpha p, r -= alpha q with partial |r|^2 */
+  MSCG_KERNEL_CG_UPDATE = 4,   /* x += alpha p, r -= alpha q with partial |r|^2 */
+  MSCG_KERNEL_SMOOTH_PRE = 5,  /* m SGS steps from zero, one tiled launch (2-D, m = 4) */
+  MSCG_KERNEL_SMOOTH_POST = 6  /* prolongation + m SGS steps, one tiled launch (2-D, m = 4) */
 };
 
 /* Launches one solver kernel `reps` times back to back on the problem's

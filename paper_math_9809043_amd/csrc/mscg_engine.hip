@@ -161,6 +161,7 @@ struct mscg_problem {
   bool owns_ws;
   bool ready;
   bool tiled;         // 2-D levels smooth with the tiled kernel
+  int tile_shape;     // its tile shape (-1: by level size)
   // per-solve state
   double eps2;
   double tol_scale;   // mixed: 1 / |r|^2 of the current outer iteration
@@ -273,9 +274,9 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
     if (e != hipSuccess && *rc == MSCG_OK) *rc = fail(MSCG_E_DEVICE, "precond level %d: %s", k, hipGetErrorString(e));
     return e == hipSuccess;
   };
-  const bool tiled = P->tiled && L.nz == 1;
+  const bool tiled = P->tiled && smooth_tile_supported(L.nz, L.tz != nullptr, m);
   if (tiled) {
-    if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->stream))) return nullptr;
+    if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->tile_shape, P->stream))) return nullptr;
   } else {
     for (int h = 0; h <= 2 * m; ++h)
       if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream))) return nullptr;
@@ -284,7 +285,7 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
   *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
   if (*rc) return nullptr;
   if (tiled) {
-    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->stream))) return nullptr;
+    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->tile_shape, P->stream))) return nullptr;
     return w;
   }
   if (!chk(launch_prolong<R>(L, X, xs[k + 1], z, P->stream))) return nullptr;
@@ -558,6 +559,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   {
     const char* e = getenv("MSCG_UNTILED");
     P->tiled = !(e && e[0] == '1');
+    const char* t = getenv("MSCG_TILE_SHAPE");
+    P->tile_shape = t ? atoi(t) : -1;
   }
   *out = P;
   return MSCG_OK;
@@ -859,10 +862,16 @@ int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* a
   if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
   if (level < 0 || level >= P->nlev) return fail(MSCG_E_ARG, "level out of range");
   if (reps < 1) return fail(MSCG_E_ARG, "reps must be >= 1");
-  if ((kernel == MSCG_KERNEL_RESTRICT || kernel == MSCG_KERNEL_PROLONG) && level + 1 >= P->nlev)
-    return fail(MSCG_E_ARG, "transfer kernels need a coarser level");
+  if ((kernel == MSCG_KERNEL_RESTRICT || kernel == MSCG_KERNEL_PROLONG || kernel == MSCG_KERNEL_SMOOTH_PRE ||
+       kernel == MSCG_KERNEL_SMOOTH_POST) && level + 1 >= P->nlev)
+    return fail(MSCG_E_ARG, "transfer and smoothing kernels need a coarser level");
+  if ((kernel == MSCG_KERNEL_SMOOTH_PRE || kernel == MSCG_KERNEL_SMOOTH_POST) &&
+      !smooth_tile_supported(P->lev[level].nz, P->g.dim == 3, P->o.smooth_steps))
+    return fail(MSCG_E_ARG, "level %d has no tiled smoother", level);
   const bool fp32 = mixed(P) && level > 0;
   if (fp32 && kernel != MSCG_KERNEL_SMOOTH_HALF) return fail(MSCG_E_ARG, "FP32 timing covers the smoother only");
+  if (mixed(P) && (kernel == MSCG_KERNEL_SMOOTH_PRE || kernel == MSCG_KERNEL_SMOOTH_POST))
+    return fail(MSCG_E_ARG, "tiled smoother timing needs an FP64 problem");
   LevelH& L = P->lev[level];
   const double w = fp32 ? 4.0 : 8.0;
   const double n = L.n;
@@ -886,6 +895,14 @@ int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* a
         return launch_prolong<double>(lv64(P, level), xfer(P, level), P->lev[level + 1].x, L.z, P->stream);
       case MSCG_KERNEL_CG_UPDATE:
         return launch_cg_update<double>(L.x, L.r, L.p, L.q, L.n, L.sc, P->part, nb, P->stream);
+      case MSCG_KERNEL_SMOOTH_PRE:
+        return launch_smooth_tile<double>(lv64(P, level), nullptr, L.r, nullptr, nullptr, L.z, P->o.smooth_steps,
+                                          P->tile_shape, P->stream);
+      case MSCG_KERNEL_SMOOTH_POST: {
+        const Xfer X = xfer(P, level);
+        return launch_smooth_tile<double>(lv64(P, level), &X, L.r, L.z, P->lev[level + 1].x, L.w,
+                                          P->o.smooth_steps, P->tile_shape, P->stream);
+      }
       default:
         return hipErrorInvalidValue;
     }
@@ -897,6 +914,8 @@ int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* a
     case MSCG_KERNEL_RESTRICT: bytes = w * (faces + 2.0 * n + (double)P->lev[level + 1].n); break;
     case MSCG_KERNEL_PROLONG: bytes = w * (2.0 * n + (double)P->lev[level + 1].n); break;
     case MSCG_KERNEL_CG_UPDATE: bytes = w * 6.0 * n; break;                            // x, r, p, q in; x, r out
+    case MSCG_KERNEL_SMOOTH_PRE: bytes = w * (faces + 2.0 * n); break;                  // T, r in; z out
+    case MSCG_KERNEL_SMOOTH_POST: bytes = w * (faces + 3.0 * n + (double)P->lev[level + 1].n); break;  // T, r, z, y; w
     default: return fail(MSCG_E_ARG, "unknown kernel id %d", kernel);
   }
   HIP_TRY(launch());  // warm

@@ -114,10 +114,13 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s);
 // m symmetric Gauss-Seidel steps (2m+1 red-black half sweeps) on a 2-D level,
 // temporally blocked in LDS.  X == nullptr: pre-smoothing from zero into zout;
 // otherwise post-smoothing from zin + E y into zout (zout must not alias zin).
-// hipErrorNotSupported for 3-D levels or when the tile does not fit LDS.
+// Tiles are built for m = 4; smooth_tile_supported says whether a level can use
+// them (hipErrorNotSupported otherwise).  shape: tile shape 0..3, or -1 to
+// choose by the level size.
+bool smooth_tile_supported(int nz, bool has_tz, int m);
 template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, int m,
-                              hipStream_t s);
+                              int shape, hipStream_t s);
 
 // Number of blocks (= partials) of a grid-wide reduction over n cells.
 inline int reduce_blocks(long long n) {

@@ -2,14 +2,21 @@
 //
 // m symmetric Gauss-Seidel steps (eq. 2.3 splitting, Section 3) are 2m+1
 // red-black half sweeps.  Instead of one grid-wide launch per half sweep, each
-// workgroup loads a tile of TW x TH cells plus a halo of H = 2m+1 cells (r,
-// the face transmissibilities and, after the coarse correction, z) into LDS,
-// runs all 2m+1 half sweeps there, and writes back the tile.  A half sweep
-// moves information by one cell, so after 2m+1 of them the tile's values are
-// exactly those of the global sweeps; halo cells are scratch.  Neighbours
-// outside the loaded region contribute nothing (their influence cannot reach
-// the tile).  The post-smoothing variant also applies the prolongation
-// z = z_pre + E y while loading.
+// workgroup takes a tile of TW x TH cells plus a halo of H = 2m+1 cells, runs
+// all 2m+1 half sweeps on it, and writes back the tile.  A half sweep moves
+// information by one cell, so after 2m+1 of them the tile's values equal those
+// of the grid-wide sweeps; halo cells are scratch.  Neighbours outside the
+// loaded region contribute nothing (their influence cannot reach the tile).
+//
+// Layout: thread (k, row group) owns the k-th red and the k-th black cell of
+// each of its rows and keeps their four neighbour coefficients (zero across
+// the domain or region edge), diagonal and r in registers, all loaded in one
+// batch.  z lives in LDS split by colour, so the cells a half sweep updates
+// are contiguous and their neighbours are contiguous in the other colour's
+// array.  The update is z = (r + sum T z_nb) / d with the terms in the same
+// order as the grid-wide half sweep, so both give the same bits.  The
+// post-smoothing variant also applies the prolongation z = z_pre + E y while
+// loading.
 #include <hip/hip_runtime.h>
 
 #include "mscg_kernels.h"
@@ -18,128 +25,158 @@ namespace mscg {
 
 namespace {
 
-constexpr int kTW = 64, kTH = 32;       // tile
-constexpr int kBX = 64, kBY = 8;        // threads: 64 x 8 = 512
+constexpr int kHalo = 9;  // 2m + 1 for m = 4
 
-template <typename R, bool POST>
-__global__ void __launch_bounds__(kBX* kBY) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
-                                                           const R* __restrict__ zin, const R* __restrict__ y,
-                                                           R* __restrict__ zout, int halo, int nsweep) {
-  extern __shared__ __align__(16) unsigned char lds[];
+template <typename R, bool POST, int TW, int TH, int BX, int BY>
+__global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
+                                                         const R* __restrict__ zin, const R* __restrict__ y,
+                                                         R* __restrict__ zout) {
+  constexpr int MW = TW + 2 * kHalo, MH = TH + 2 * kHalo;
+  constexpr int HW = (MW + 1) / 2;         // cells of one colour per region row, upper bound
+  constexpr int NR = (MH + BY - 1) / BY;   // region rows per thread
+  static_assert(HW <= BX, "tile too wide for the thread layout");
+  __shared__ R zc[2][MH][HW];              // [colour][region row][index within the colour]
   const int nx = L.nx, ny = L.ny;
-  const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
-  const int rx0 = max(x0 - halo, 0), ry0 = max(y0 - halo, 0);
-  const int rx1 = min(x0 + kTW + halo, nx), ry1 = min(y0 + kTH + halo, ny);
-  const int RW = rx1 - rx0, RH = ry1 - ry0;
-  const int MW = kTW + 2 * halo;  // LDS row pitch (cells)
-  R* zs = reinterpret_cast<R*>(lds);
-  R* rs = zs + (size_t)MW * (kTH + 2 * halo);
-  R* txs = rs + (size_t)MW * (kTH + 2 * halo);         // (RH) rows of (RW + 1) faces, pitch MW + 1
-  R* tys = txs + (size_t)(MW + 1) * (kTH + 2 * halo);  // (RH + 1) rows of RW faces, pitch MW
-  const int tx = threadIdx.x % kBX, ty = threadIdx.x / kBX;
+  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const int rx0 = max(x0 - kHalo, 0), ry0 = max(y0 - kHalo, 0);
+  const int RW = min(x0 + TW + kHalo, nx) - rx0, RH = min(y0 + TH + kHalo, ny) - ry0;
+  const int k = threadIdx.x % BX, ty = threadIdx.x / BX;
 
-  // load the region
-  for (int lj = ty; lj < RH; lj += kBY) {
+  // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
+  // within its colour.  The thread's cell of colour c in row lj is
+  // li = 2k + ((rx0 + ry0 + lj + c) & 1).
+  int xI0[2], xI1[2];
+  R xw0[2], xw1[2];
+  if (POST) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
+  }
+  R cw[NR][2], ce[NR][2], cs[NR][2], cn[NR][2], dg[NR][2], rr[NR][2];
+#pragma unroll
+  for (int b = 0; b < NR; ++b) {
+    const int lj = ty + BY * b;
     const int j = ry0 + lj;
-    for (int li = tx; li < RW; li += kBX) {
-      const int i = rx0 + li;
-      const int c = i + nx * j;
-      rs[lj * MW + li] = r[c];
-      if (POST) {
-        int I0, I1, J0, J1;
-        R wi0, wi1, wj0, wj1;
-        ext_weights<R>(i, X.sx, X.cnx, X.interp, I0, wi0, I1, wi1);
-        ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
-        // same products and order as the grid-wide prolongation
-        R v = R(0);
-        const int Js[2] = {J0, J1};
-        const R wj[2] = {wj0, wj1};
-        for (int b = 0; b < 2; ++b) {
-          if (wj[b] == R(0)) continue;
-          if (wi0 != R(0)) v += (R(1) * wj[b] * wi0) * y[I0 + X.cnx * Js[b]];
-          if (wi1 != R(0)) v += (R(1) * wj[b] * wi1) * y[I1 + X.cnx * Js[b]];
+    int J0 = 0, J1 = 0;
+    R wj0 = R(0), wj1 = R(0);
+    if (POST && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = (rx0 + ry0 + lj + c) & 1;
+      const int li = 2 * k + q;
+      cw[b][c] = ce[b][c] = cs[b][c] = cn[b][c] = R(0);
+      dg[b][c] = R(1);
+      rr[b][c] = R(0);
+      if (lj < RH && li < RW) {
+        const int i = rx0 + li;
+        const int fx = i + (nx + 1) * j, fy = i + nx * j;
+        const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
+        dg[b][c] = tw + te + ts + tn;
+        if (i > 0 && li > 0) cw[b][c] = tw;
+        if (i < nx - 1 && li < RW - 1) ce[b][c] = te;
+        if (j > 0 && lj > 0) cs[b][c] = ts;
+        if (j < ny - 1 && lj < RH - 1) cn[b][c] = tn;
+        rr[b][c] = r[i + nx * j];
+        if (POST) {
+          // same products, in the same order, as the grid-wide prolongation
+          R v = R(0);
+          if (wj0 != R(0)) {
+            if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * y[xI0[q] + X.cnx * J0];
+            if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * y[xI1[q] + X.cnx * J0];
+          }
+          if (wj1 != R(0)) {
+            if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * y[xI0[q] + X.cnx * J1];
+            if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * y[xI1[q] + X.cnx * J1];
+          }
+          zc[c][lj][k] = zin[i + nx * j] + v;
         }
-        zs[lj * MW + li] = zin[c] + v;
       }
     }
-    for (int li = tx; li <= RW; li += kBX) txs[lj * (MW + 1) + li] = L.tx[(rx0 + li) + (nx + 1) * j];
   }
-  for (int lj = ty; lj <= RH; lj += kBY)
-    for (int li = tx; li < RW; li += kBX) tys[lj * MW + li] = L.ty[(rx0 + li) + nx * (ry0 + lj)];
   __syncthreads();
 
-  // 2m+1 half sweeps: colour of cell (i, j) is (i + j) & 1, red first
-  for (int h = 0; h < nsweep; ++h) {
-    const int colour = h & 1;
+  // 2m+1 half sweeps, red (colour 0) first; neighbours are of the other
+  // colour: (li - 1, li + 1) in the row, li in the rows above and below
+  for (int h = 0; h < kHalo; ++h) {
+    const int c = h & 1, oc = c ^ 1;
     const bool first = !POST && h == 0;
-    for (int lj = ty; lj < RH; lj += kBY) {
-      const int j = ry0 + lj;
-      // first local column of this colour in the row
-      const int start = ((rx0 + j + colour) & 1);
-      for (int li = start + 2 * tx; li < RW; li += 2 * kBX) {
-        const int i = rx0 + li;
-        const R tw = txs[lj * (MW + 1) + li], te = txs[lj * (MW + 1) + li + 1];
-        const R ts = tys[lj * MW + li], tn = tys[(lj + 1) * MW + li];
-        const R d = tw + te + ts + tn;
+#pragma unroll
+    for (int b = 0; b < NR; ++b) {
+      const int lj = ty + BY * b;
+      const int li = 2 * k + ((rx0 + ry0 + lj + c) & 1);
+      if (lj < RH && li < RW) {
         R o = R(0);
         if (!first) {
-          if (i > 0 && li > 0) o += tw * zs[lj * MW + li - 1];
-          if (i < nx - 1 && li < RW - 1) o += te * zs[lj * MW + li + 1];
-          if (j > 0 && lj > 0) o += ts * zs[(lj - 1) * MW + li];
-          if (j < ny - 1 && lj < RH - 1) o += tn * zs[(lj + 1) * MW + li];
+          const int w = li > 0 ? (li - 1) >> 1 : 0;
+          const int e = min((li + 1) >> 1, HW - 1);
+          const int s = lj > 0 ? lj - 1 : 0, n = min(lj + 1, MH - 1);
+          if (cw[b][c] != R(0)) o += cw[b][c] * zc[oc][lj][w];
+          if (ce[b][c] != R(0)) o += ce[b][c] * zc[oc][lj][e];
+          if (cs[b][c] != R(0)) o += cs[b][c] * zc[oc][s][k];
+          if (cn[b][c] != R(0)) o += cn[b][c] * zc[oc][n][k];
         }
-        zs[lj * MW + li] = (rs[lj * MW + li] + o) / d;
+        zc[c][lj][k] = (rr[b][c] + o) / dg[b][c];
       }
     }
     __syncthreads();
   }
 
-  // write the tile
-  for (int lj = ty; lj < kTH; lj += kBY) {
-    const int j = y0 + lj;
-    if (j >= ny) break;
-    for (int li = tx; li < kTW; li += kBX) {
-      const int i = x0 + li;
-      if (i >= nx) break;
-      zout[i + nx * j] = zs[(j - ry0) * MW + (i - rx0)];
+  // write back the tile's own cells
+#pragma unroll
+  for (int b = 0; b < NR; ++b) {
+    const int lj = ty + BY * b;
+    const int j = ry0 + lj;
+    if (lj >= RH || j < y0 || j >= y0 + TH) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int li = 2 * k + ((rx0 + ry0 + lj + c) & 1);
+      const int i = rx0 + li;
+      if (li < RW && i >= x0 && i < x0 + TW) zout[i + nx * j] = zc[c][lj][k];
     }
   }
 }
 
-}  // namespace
-
-size_t smooth_tile_lds_bytes(int halo, size_t elem) {
-  const size_t MW = kTW + 2 * halo, MH = kTH + 2 * halo;
-  return elem * (MW * MH * 2 + (MW + 1) * MH + MW * (MH + 1));
-}
-
-template <typename R>
-hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout,
-                              int m, hipStream_t s) {
-  if (L.tz || L.nz != 1) return hipErrorNotSupported;
-  const int halo = 2 * m + 1;
-  const size_t bytes = smooth_tile_lds_bytes(halo, sizeof(R));
-  if (bytes > 156 * 1024) return hipErrorNotSupported;
-  static bool attr[2][2] = {{false, false}, {false, false}};
-  const int ri = sizeof(R) == 8 ? 1 : 0, pi = X ? 1 : 0;
-  const void* fn = X ? (const void*)k_smooth_tile<R, true> : (const void*)k_smooth_tile<R, false>;
-  if (!attr[ri][pi]) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
-    if (e != hipSuccess) return e;
-    attr[ri][pi] = true;
-  }
-  const dim3 grid((L.nx + kTW - 1) / kTW, (L.ny + kTH - 1) / kTH);
-  const dim3 block(kBX * kBY);
+template <typename R, int TW, int TH, int BX, int BY>
+hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, hipStream_t s) {
+  const dim3 grid((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
+  const dim3 block(BX * BY);
   if (X)
-    hipLaunchKernelGGL((k_smooth_tile<R, true>), grid, block, bytes, s, L, *X, r, zin, y, zout, halo, 2 * m + 1);
+    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout);
   else
-    hipLaunchKernelGGL((k_smooth_tile<R, false>), grid, block, bytes, s, L, Xfer{}, r, zin, y, zout, halo, 2 * m + 1);
+    hipLaunchKernelGGL((k_smooth_tile<R, false, TW, TH, BX, BY>), grid, block, 0, s, L, Xfer{}, r, zin, y, zout);
   return hipGetLastError();
 }
 
+// Tile shapes: 0 = 64 x 32 (512 threads), 1 = 110 x 38 (512 threads, region
+// rows of exactly 128 cells), 2 = 46 x 14 (256 threads), 3 = 14 x 14 (256
+// threads).  Larger tiles re-read less halo but hold more registers per
+// thread, which caps the waves per CU; measured on MI355X (1024^2 and 256^2
+// levels), the small-register shapes win: 46 x 14 on the largest levels,
+// 14 x 14 below.
+int auto_shape(int nx, int ny) {
+  const long long cells = (long long)nx * ny;
+  return cells >= (1LL << 19) ? 2 : 3;
+}
+
+}  // namespace
+
+bool smooth_tile_supported(int nz, bool has_tz, int m) { return nz == 1 && !has_tz && 2 * m + 1 == kHalo; }
+
+template <typename R>
+hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout,
+                              int m, int shape, hipStream_t s) {
+  if (!smooth_tile_supported(L.nz, L.tz != nullptr, m)) return hipErrorNotSupported;
+  if (shape < 0 || shape > 3) shape = auto_shape(L.nx, L.ny);
+  switch (shape) {
+    case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s);
+    case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s);
+    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s);
+    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s);
+  }
+}
+
 template hipError_t launch_smooth_tile<double>(const Lv<double>&, const Xfer*, const double*, const double*,
-                                               const double*, double*, int, hipStream_t);
+                                               const double*, double*, int, int, hipStream_t);
 template hipError_t launch_smooth_tile<float>(const Lv<float>&, const Xfer*, const float*, const float*,
-                                              const float*, float*, int, hipStream_t);
+                                              const float*, float*, int, int, hipStream_t);
 
 }  // namespace mscg

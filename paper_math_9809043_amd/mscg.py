@@ -55,7 +55,8 @@ EXPORTS = [
     "mscg_apply_operator", "mscg_apply_smoother", "mscg_restrict_residual", "mscg_prolong_add",
     "mscg_apply_preconditioner", "mscg_time_kernel",
 ]
-KERNEL_SMOOTH_HALF, KERNEL_SPMV, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_CG_UPDATE = range(5)
+(KERNEL_SMOOTH_HALF, KERNEL_SPMV, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_CG_UPDATE, KERNEL_SMOOTH_PRE,
+ KERNEL_SMOOTH_POST) = range(7)
 
 _lib = None
 

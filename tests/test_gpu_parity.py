@@ -257,12 +257,20 @@ def test_batch_matches_single():
     ("channel128_const", lambda: synth.channelised_2d(1, 128), {"interp": 1}),
 ], ids=["ragged96x40", "smooth512", "channel128_const"])
 def test_tiled_smoother_matches_half_sweeps(name, make, opt, monkeypatch):
-    """The LDS-tiled smoother reproduces the grid-wide half sweeps bitwise
-    (a missing barrier or a short halo would break this)."""
-    case(f"tiled vs untiled {name}")
+    """The LDS-tiled smoother, in every tile shape, reproduces the grid-wide
+    half sweeps bitwise (a missing barrier, a short halo or a wrong ragged
+    tile edge would break this)."""
     P = make()
-    st_t, x_t, _ = gpu_solve(P, **opt)
     monkeypatch.setenv("MSCG_UNTILED", "1")
+    case(f"untiled {name}")
     st_u, x_u, _ = gpu_solve(P, **opt)
-    assert st_t.level_iters == st_u.level_iters
-    assert np.array_equal(x_t, x_u), np.abs(x_t - x_u).max()
+    monkeypatch.delenv("MSCG_UNTILED")
+    for shape in ("auto", "0", "1", "2", "3"):
+        case(f"tiled shape {shape} {name}")
+        if shape == "auto":
+            monkeypatch.delenv("MSCG_TILE_SHAPE", raising=False)
+        else:
+            monkeypatch.setenv("MSCG_TILE_SHAPE", shape)
+        st_t, x_t, _ = gpu_solve(P, **opt)
+        assert st_t.level_iters == st_u.level_iters
+        assert np.array_equal(x_t, x_u), (shape, np.abs(x_t - x_u).max())
