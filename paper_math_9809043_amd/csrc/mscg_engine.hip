@@ -162,6 +162,7 @@ struct mscg_problem {
   bool ready;
   bool tiled;         // 2-D levels smooth with the tiled kernel
   int tile_shape;     // its tile shape (-1: by level size)
+  int small_variant;  // one-workgroup kernel of 2-D small levels (0 colour-split, 1 cell-strided)
   // per-solve state
   double eps2;
   double tol_scale;   // mixed: 1 / |r|^2 of the current outer iteration
@@ -251,6 +252,7 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
     d.iters = P->dcount;
     d.calls = P->dcount + MSCG_MAX_LEVELS;
     d.status = P->dflags + 2;
+    d.variant = P->small_variant;
     const hipError_t e = launch_small_reg<R>(d, P->stream);
     if (e == hipErrorNotSupported) HIP_TRY(launch_small_pcg<R>(d, P->stream));
     else HIP_TRY(e);
@@ -561,6 +563,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
     P->tiled = !(e && e[0] == '1');
     const char* t = getenv("MSCG_TILE_SHAPE");
     P->tile_shape = t ? atoi(t) : -1;
+    const char* v = getenv("MSCG_SMALL_VARIANT");
+    P->small_variant = v ? atoi(v) : 0;
   }
   *out = P;
   return MSCG_OK;

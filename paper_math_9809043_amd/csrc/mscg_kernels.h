@@ -64,6 +64,7 @@ struct SmallDesc {
   int ncoarse;
   long long *iters, *calls;
   int* status;
+  int variant;  // one-workgroup kernel for 2-D levels: 0 colour-split, 1 cell-strided
 };
 
 hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s);
@@ -110,6 +111,11 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s);
 // (at most 4096 cells); hipErrorNotSupported when the hierarchy does not fit.
 template <typename R>
 hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s);
+
+// The same for a 2-D level with at most 2048 cells of each colour (colour-
+// split LDS layout); hipErrorNotSupported otherwise.
+template <typename R>
+hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s);
 
 // m symmetric Gauss-Seidel steps (2m+1 red-black half sweeps) on a 2-D level,
 // temporally blocked in LDS.  X == nullptr: pre-smoothing from zero into zout;

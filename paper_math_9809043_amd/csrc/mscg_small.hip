@@ -295,11 +295,12 @@ __global__ void __launch_bounds__(kThreads, 1) k_small_reg(RegArgs a) {
 
 template <typename R>
 hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
-  // The FP32 instantiation gave results that changed from run to run on the
-  // GPU (identical inputs, occasional non-finite reductions) while the FP64
-  // one is bitwise repeatable; until the cause is found, FP32 levels use the
+  // 2-D levels go to the colour-split kernel (both precisions).  The FP32
+  // instantiation of the cell-strided kernel below gave results that changed
+  // from run to run on the GPU (identical inputs, occasional non-finite
+  // reductions) while its FP64 one is bitwise repeatable; until the cause is
+  // found, FP32 levels that the colour-split kernel does not take use the
   // generic one-workgroup solver.
-  if (sizeof(R) != sizeof(double)) return hipErrorNotSupported;
   const int ks = d.ks, L = d.nlev - 1;
   if (ks + 1 != L) return hipErrorNotSupported;
   const Lv<R>& V = d.L[ks];
@@ -307,6 +308,11 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
   const Xfer& X = d.X[ks];
   const int nc = X.cnx * X.cny * X.cnz;
   if (nc > 1024) return hipErrorNotSupported;
+  if (d.variant == 0) {
+    const hipError_t e = launch_small_2d<R>(d, s);
+    if (e != hipErrorNotSupported) return e;
+  }
+  if (sizeof(R) != sizeof(double)) return hipErrorNotSupported;
   RegArgs a{};
   a.dim = V.tz ? 3 : 2;
   a.nx = V.nx; a.ny = V.ny; a.nz = V.nz; a.n = V.n;

@@ -274,3 +274,26 @@ def test_tiled_smoother_matches_half_sweeps(name, make, opt, monkeypatch):
         st_t, x_t, _ = gpu_solve(P, **opt)
         assert st_t.level_iters == st_u.level_iters
         assert np.array_equal(x_t, x_u), (shape, np.abs(x_t - x_u).max())
+
+
+@pytest.mark.parametrize("name,make,opt", [
+    ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
+    ("rect288x160", lambda: synth.smoothed_lognormal_2d(7, 288, 160, lo=-3, hi=3), {}),
+    ("smooth256_const", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"interp": 1}),
+], ids=["smooth256", "rect288x160", "smooth256_const"])
+def test_small_level_kernels_agree(name, make, opt, monkeypatch):
+    """The colour-split and the cell-strided one-workgroup solvers of the last
+    inner level give the same solve up to rounding, and both match the oracle."""
+    P = make()
+    ref = oracle.solve(P, **oracle_opts(opt))
+    out = {}
+    for variant in ("0", "1"):
+        case(f"small-level kernel {variant} {name}")
+        monkeypatch.setenv("MSCG_SMALL_VARIANT", variant)
+        st, x, prob = gpu_solve(P, **opt)
+        assert prob.n_levels >= 3
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
+        assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) <= 1e-8
+        out[variant] = x
+    assert np.linalg.norm(out["0"] - out["1"]) / np.linalg.norm(out["1"]) <= 1e-8
