@@ -22,6 +22,33 @@ struct Lv {
   const R *tx, *ty, *tz;
 };
 
+// DPP move of a double (two 32-bit halves); lanes without a source read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, exact order fixed by the lane pattern; valid in lane 63.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_d<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_d<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_d<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row sum
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the sum
+  return v;
+}
+
+// wave_sum_dpp broadcast to every lane of the wave
+__device__ __forceinline__ double wave_total(double v) {
+  v = wave_sum_dpp(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // Diagonal and off-diagonal sum of the 5/7-point finite-volume operator at
 // cell c = (i, j, k): (A x)_c = diag * x_c - off, off = sum_f T_f x_nb over
 // interior faces (Section 3).  A boundary face contributes T_f to the

@@ -257,6 +257,127 @@ __global__ void __launch_bounds__(256) k_chol_inverse(const double* __restrict__
   for (int k = lane; k < n; k += kWave) Ainv[(long long)c * n + k] = w[k];
 }
 
+// Banded coarsest factorisation.  Every nonzero A[i][k] of the 5/7-point
+// operator has |i - k| <= b (b = nx in 2-D, nx ny in 3-D, natural order), and
+// the Cholesky factor keeps that band.  One workgroup; the b + 1 rows j..j+b
+// that step j updates sit in LDS as a window (row i in slot i mod (b+1),
+// entry t holding column i - b + t), so a step touches LDS only: scale column
+// j, update the trailing b x b triangle, and refill the freed slot with row
+// j + b + 1 of A.  Outputs: Lb[i (b+1) + t] = L[i][i - b + t] (row band) and
+// Lt[i (b+1) + t] = L[i + t][i] (column band), zero outside the matrix.
+// status[0] = 1 if A is not positive definite.
+__global__ void __launch_bounds__(1024) k_chol_band(const double* __restrict__ A, int n, int b,
+                                                    double* __restrict__ Lb, double* __restrict__ Lt,
+                                                    int* __restrict__ status) {
+  extern __shared__ double win[];  // (b + 1) x (b + 1)
+  const int W = b + 1, tid = threadIdx.x, nt = blockDim.x;
+  auto row_entry = [&](int i, int t) {  // A[i][i - b + t], zero outside the matrix
+    const int k = i - b + t;
+    return (i < n && k >= 0) ? A[(long long)i * n + k] : 0.0;
+  };
+  for (int e = tid; e < W * W; e += nt) win[e] = row_entry(e / W, e % W);
+  __syncthreads();
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    const int sj = j % W;
+    const double djj = win[sj * W + b];
+    if (!(djj > 0.0)) { bad = 1; break; }  // every thread reads the same value
+    const double ljj = sqrt(djj);
+    // scale column j of rows j+1..j+b; row j is final
+    for (int t = tid; t < b; t += nt) {
+      const int i = j + 1 + t;
+      if (i < n) win[(i % W) * W + (j - i + b)] /= ljj;
+    }
+    for (int t = tid; t < W; t += nt) Lb[(long long)j * W + t] = t == b ? ljj : win[sj * W + t];
+    __syncthreads();
+    // column j of L, then the trailing update a_ik -= l_ij l_kj (j < k <= i <= j+b),
+    // and row j + b + 1 of A into the freed slot
+    for (int t = tid; t < W; t += nt) {
+      const int i = j + t;
+      Lt[(long long)j * W + t] = t == 0 ? ljj : (i < n ? win[(i % W) * W + (j - i + b)] : 0.0);
+    }
+    for (int e = tid; e < b * b; e += nt) {
+      const int ii = e / b, kk = e - ii * b;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      if (i >= n) continue;
+      const int si = i % W, sk = k % W;
+      win[si * W + (k - i + b)] -= win[si * W + (j - i + b)] * win[sk * W + (j - k + b)];
+    }
+    for (int t = tid; t < W; t += nt) win[sj * W + t] = row_entry(j + W, t);
+    __syncthreads();
+  }
+  if (tid == 0) status[0] = bad;
+}
+
+// A^-1 from the banded factor, one wave per column c: L w = e_c forward, then
+// L^T x = w backward.  Lane l holds the latest w_k (x_k) with k = l mod 64;
+// with b <= 64 the band of row i contains at most one such k per lane, so a
+// step is one product per lane and a DPP wave sum.  The four waves of a
+// workgroup handle consecutive columns and walk the rows together: chunks of
+// band rows are staged in LDS for all four.
+constexpr int kBandChunk = 32;
+
+__global__ void __launch_bounds__(256) k_band_inverse(const double* __restrict__ Lb, const double* __restrict__ Lt,
+                                                      double* __restrict__ Ainv, int n, int b) {
+  __shared__ double rows[kBandChunk][65];
+  __shared__ double wbuf[4][MSCG_COARSE_CAP];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int W = b + 1;
+  const int c0 = blockIdx.x * 4, c = c0 + wave;
+  double* w = wbuf[wave];
+  for (int k = lane; k < n; k += kWave) w[k] = 0.0;
+  double reg = 0.0;
+  // forward: w_i = (delta_ic - sum_{k in [max(c, i-b), i)} L[i][k] w_k) / L[i][i]
+  for (int i0 = c0; i0 < n; i0 += kBandChunk) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBandChunk * W; e += blockDim.x) {
+      const int r = e / W, t = e - r * W, i = i0 + r;
+      rows[r][t] = i < n ? Lb[(long long)i * W + t] : 0.0;
+    }
+    __syncthreads();
+    if (c >= n) continue;
+    for (int r = 0; r < kBandChunk; ++r) {
+      const int i = i0 + r;
+      if (i >= n) break;
+      if (i < c) continue;
+      const int d = (lane - i) & (kWave - 1), k = i - kWave + d;
+      const double term = (k >= c && k >= i - b) ? rows[r][k - i + b] * reg : 0.0;
+      const double s = wave_total(term);
+      const double wi = ((i == c ? 1.0 : 0.0) - s) / rows[r][b];
+      if ((i & (kWave - 1)) == lane) {
+        reg = wi;
+        w[i] = wi;
+      }
+    }
+  }
+  // backward: x_i = (w_i - sum_{k in (i, min(n-1, i+b)]} L[k][i] x_k) / L[i][i]
+  reg = 0.0;
+  for (int i0 = n - 1; i0 >= 0; i0 -= kBandChunk) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBandChunk * W; e += blockDim.x) {
+      const int r = e / W, t = e - r * W, i = i0 - r;
+      rows[r][t] = i >= 0 ? Lt[(long long)i * W + t] : 0.0;
+    }
+    __syncthreads();
+    if (c >= n) continue;
+    for (int r = 0; r < kBandChunk; ++r) {
+      const int i = i0 - r;
+      if (i < 0) break;
+      const int k = i + 1 + ((lane - i - 1) & (kWave - 1));
+      const double term = (k <= i + b && k < n) ? rows[r][k - i] * reg : 0.0;
+      const double s = wave_total(term);
+      const double xi = (w[i] - s) / rows[r][0];
+      if ((i & (kWave - 1)) == lane) {
+        reg = xi;
+        w[i] = xi;
+      }
+    }
+  }
+  if (c < n)
+    for (int k = lane; k < n; k += kWave) Ainv[(long long)c * n + k] = w[k];
+}
+
 // ---------------------------------------------------------------------------
 // Solve-phase kernels (grid-wide).  Reductions write one partial per block;
 // k_finish_* sums them in block order in one workgroup, so every result is
@@ -719,6 +840,16 @@ hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, d
   if (L.n > MSCG_COARSE_CAP) return hipErrorInvalidValue;
   const long long nn = (long long)L.n * L.n;
   hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
+  // bandwidth in natural order; the two band copies of the factor go to Lrows
+  const int b = L.nz > 1 ? L.nx * L.ny : (L.ny > 1 ? L.nx : 1);
+  if (b <= 64 && 2LL * (b + 1) * L.n <= nn) {
+    const int W = b + 1;
+    hipLaunchKernelGGL(k_chol_band, dim3(1), dim3(1024), (size_t)W * W * sizeof(double), s, A, L.n, b, Lrows,
+                       Lrows + (long long)L.n * W, status);
+    hipLaunchKernelGGL(k_band_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, Lrows, Lrows + (long long)L.n * W,
+                       Ainv, L.n, b);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, A, L.n, status);
   hipLaunchKernelGGL(k_factor_rows, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, Lrows, L.n);
   hipLaunchKernelGGL(k_chol_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, A, Lrows, Ainv, L.n);

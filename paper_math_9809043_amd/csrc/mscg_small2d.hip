@@ -61,25 +61,6 @@ struct Small2dArgs {
   int off_z, off_p, off_res, off_tx1, off_g, off_y, off_part, off_wx, off_wy, off_ci, off_cw, off_ri, off_rw;
 };
 
-// DPP move of a double (two 32-bit halves); lanes without a source read 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over the wave, exact order fixed by the lane pattern; valid in lane 63.
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_d<0x111, 0xf>(v);  // row_shr:1
-  v += dpp_d<0x112, 0xf>(v);  // row_shr:2
-  v += dpp_d<0x114, 0xf>(v);  // row_shr:4
-  v += dpp_d<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row sum
-  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the sum
-  return v;
-}
-
 template <typename R>
 __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
