@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -113,7 +114,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
     add(fx * 8); add(fy * 8); if (fz) add(fz * 8);
     if (mixed) { add(fx * 4); add(fy * 4); if (fz) add(fz * 4); }
     const bool fp64_vec = !mixed || l == 0;
-    for (int v = 0; v < 6; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
+    for (int v = 0; v < 7; ++v) add((size_t)L.n * (fp64_vec ? 8 : 4));
     if (mixed && l == 0) { add((size_t)L.n * 4); add((size_t)L.n * 4); add((size_t)L.n * 4); }  // scaled r, iterate, output
     add(sizeof(Scal));
   }
@@ -133,8 +134,9 @@ struct LevelH {
   int sx, sy, sz;
   double *tx, *ty, *tz;
   float *tx32, *ty32, *tz32;
-  double *x, *r, *z, *p, *q, *w;  // FP64 vectors (FP64 mode, or level 0); w: residual / post-smoothing output
-  float *x32, *r32, *z32, *p32, *q32, *w32;  // FP32 vectors (mixed inner levels; level 0: r32, z32, w32)
+  double *x, *r, *z, *p, *q, *w, *p2;  // FP64 vectors (FP64 mode, or level 0); w: residual / post-smoothing
+                                       // output; p, p2: directions, alternating
+  float *x32, *r32, *z32, *p32, *q32, *w32, *p232;  // FP32 vectors (mixed inner levels; level 0: r32, z32, w32)
   Scal* sc;
 };
 
@@ -152,6 +154,8 @@ struct mscg_problem {
   double* part;
   double* b;
   int* dflags;        // [0] coarse factor status, [1] bad K, [2] small-kernel status
+  int spec_hint[MSCG_MAX_LEVELS];  // iterations of the level's last call: how many to queue ahead
+  bool queue_ahead;   // queue inner iterations ahead of their convergence test
   long long* dcount;  // [0..7] small iters, [8..15] small calls
   Scal* hsc;          // pinned mirror of one Scal
   int* hflags;        // pinned
@@ -204,6 +208,9 @@ int clear_scalars(mscg_problem* P) {
   for (int l = 0; l < P->nlev; ++l) {
     HIP_TRY(launch_fill<double>(reinterpret_cast<double*>(P->lev[l].sc), sizeof(Scal) / sizeof(double), 0.0, P->stream));
     if (P->o.flexible) HIP_TRY(launch_fill<int>(&P->lev[l].sc->flexible, 1, 1, P->stream));
+    if (mixed(P) && l > 0 && P->o.inner_rel_floor > 0.0)
+      HIP_TRY(launch_fill<double>(&P->lev[l].sc->rel_floor2, 1, P->o.inner_rel_floor * P->o.inner_rel_floor,
+                                  P->stream));
   }
   return MSCG_OK;
 }
@@ -223,11 +230,12 @@ int pcg_host(mscg_problem* P, int k);
 
 // Coarse part of the preconditioner on level k: y_{k+1} = A_{k+1}^-1 g.
 template <typename R>
-int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* const* zs, R* const* ps, R* const* qs) {
+int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* const* zs, R* const* ps, R* const* qs,
+                      const int* gate) {
   const int kc = k + 1;
   if (kc == P->nlev - 1) {
-    HIP_TRY(launch_coarse_solve<R>(P->Ainv, rs[kc], xs[kc], P->ncoarse, P->stream));
-    P->calls[kc]++;
+    HIP_TRY(launch_coarse_solve<R>(P->Ainv, rs[kc], xs[kc], P->ncoarse, P->stream, gate));
+    if (!gate) P->calls[kc]++;  // queued-ahead iterations are counted by cg_loop
     return MSCG_OK;
   }
   if (kc >= P->ks) {
@@ -253,6 +261,7 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
     d.calls = P->dcount + MSCG_MAX_LEVELS;
     d.status = P->dflags + 2;
     d.variant = P->small_variant;
+    d.gate = gate;
     const hipError_t e = launch_small_reg<R>(d, P->stream);
     if (e == hipErrorNotSupported) HIP_TRY(launch_small_pcg<R>(d, P->stream));
     else HIP_TRY(e);
@@ -268,7 +277,7 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
 // holds M_k^-1 r_k.  q is not touched, so the flexible beta can still use it.
 template <typename R>
 R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, R* const* xs, R* const* rs,
-                R* const* zs, R* const* ps, R* const* qs, int* rc) {
+                R* const* zs, R* const* ps, R* const* qs, int* rc, const int* gate) {
   const int m = P->o.smooth_steps;
   const Xfer X = xfer(P, k);
   *rc = MSCG_OK;
@@ -278,21 +287,22 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
   };
   const bool tiled = P->tiled && smooth_tile_supported(L.nz, L.tz != nullptr, m);
   if (tiled) {
-    if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->tile_shape, P->stream))) return nullptr;
+    if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->tile_shape, P->stream, gate)))
+      return nullptr;
   } else {
     for (int h = 0; h <= 2 * m; ++h)
-      if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream))) return nullptr;
+      if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream, gate))) return nullptr;
   }
-  if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream))) return nullptr;
-  *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs);
+  if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream, gate))) return nullptr;
+  *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs, gate);
   if (*rc) return nullptr;
   if (tiled) {
-    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->tile_shape, P->stream))) return nullptr;
+    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->tile_shape, P->stream, gate))) return nullptr;
     return w;
   }
-  if (!chk(launch_prolong<R>(L, X, xs[k + 1], z, P->stream))) return nullptr;
+  if (!chk(launch_prolong<R>(L, X, xs[k + 1], z, P->stream, gate))) return nullptr;
   for (int h = 0; h <= 2 * m; ++h)
-    if (!chk(launch_gs_half<R>(L, r, z, h & 1, 0, P->stream))) return nullptr;
+    if (!chk(launch_gs_half<R>(L, r, z, h & 1, 0, P->stream, gate))) return nullptr;
   return z;
 }
 
@@ -310,13 +320,13 @@ void vec_tables(mscg_problem* P, R** xs, R** rs, R** zs, R** ps, R** qs) {
 
 // Applies the level-k preconditioner to the level's residual; *out receives
 // the vector (in the level's CG precision) that holds the result.
-int apply_prec(mscg_problem* P, int k, void** out) {
+int apply_prec(mscg_problem* P, int k, void** out, const int* gate) {
   int rc = MSCG_OK;
   if (!mixed(P)) {
     double *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
     vec_tables<double>(P, xs, rs, zs, ps, qs);
     LevelH& H = P->lev[k];
-    *out = precond_host<double>(P, k, lv64(P, k), H.r, H.z, H.w, xs, rs, zs, ps, qs, &rc);
+    *out = precond_host<double>(P, k, lv64(P, k), H.r, H.z, H.w, xs, rs, zs, ps, qs, &rc, gate);
     return rc;
   }
   float *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
@@ -326,57 +336,78 @@ int apply_prec(mscg_problem* P, int k, void** out) {
     // the inner solves only need the overall accuracy; the outer CG recovers FP64)
     LevelH& L0 = P->lev[0];
     HIP_TRY(launch_scale_to_f32(L0.r, L0.r32, L0.n, L0.sc, P->stream));
-    float* z32 = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc);
+    float* z32 = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc, nullptr);
     if (rc) return rc;
     HIP_TRY(launch_scale_to_f64(z32, L0.z, L0.n, L0.sc, P->stream));
     *out = L0.z;
     return MSCG_OK;
   }
   LevelH& H = P->lev[k];
-  *out = precond_host<float>(P, k, lv32(P, k), H.r32, H.z32, H.w32, xs, rs, zs, ps, qs, &rc);
+  *out = precond_host<float>(P, k, lv32(P, k), H.r32, H.z32, H.w32, xs, rs, zs, ps, qs, &rc, gate);
   return rc;
 }
 
 // One level's CG loop (Templates Figure 2.5) on vectors of type R; the residual
-// is in r_k and the entry check has been done by the caller (sc->converged).
+// is in r_k and the entry check has been done (sc->converged).  Per iteration:
+// the preconditioner, r.z, p and A p with p.q, then the x / r update with
+// |r|^2, each reduction followed by its one-workgroup finish.  The directions
+// alternate between p and p2 (the next one is formed from the current one on
+// the fly, inside the SpMV).
+//
+// On the deepest host-driven level the iteration holds no host decision (the
+// coarse correction runs entirely on the device), so iterations are queued
+// ahead in batches, gated on the level's converged flag, and the host waits
+// once per batch: as many as the level's last call needed plus one, then two
+// at a time.  Iterations queued past convergence return at once.
 template <typename R>
-int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* q, int max_iter) {
+int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p2, R* q, int max_iter) {
   LevelH& H = P->lev[k];
   const int nb = reduce_blocks(L.n);
-  for (int it = 0; it < max_iter; ++it) {
-    void* zres = nullptr;
-    int rc = apply_prec(P, k, &zres);
-    if (rc) return rc;
-    z = static_cast<R*>(zres);
-    if (P->o.flexible && it > 0) {
-      HIP_TRY(launch_dot<R>(z, q, L.n, P->part, nb, P->stream));
-      HIP_TRY(launch_finish(P->part, nb, H.sc, kOpZq, P->stream));
+  const bool ahead = P->queue_ahead && k > 0 && (k + 1 == P->nlev - 1 || k + 1 >= P->ks);
+  const int* gate = ahead ? &H.sc->converged : nullptr;
+  R* pc = p;
+  R* pn = p2;
+  int queued = 0;
+  int rc = MSCG_OK;
+  while (queued < max_iter) {
+    int batch = 1;
+    if (ahead) batch = std::max(1, std::min(queued == 0 ? P->spec_hint[k] + 1 : 2, max_iter - queued));
+    for (int b = 0; b < batch; ++b, ++queued) {
+      void* zres = nullptr;
+      rc = apply_prec(P, k, &zres, gate);
+      if (rc) return rc;
+      z = static_cast<R*>(zres);
+      if (P->o.flexible && queued > 0)
+        HIP_TRY(launch_dot_fin<R>(z, q, L.n, P->part, nb, H.sc, kOpZq, P->stream, gate));
+      HIP_TRY(launch_dot_fin<R>(r, z, L.n, P->part, nb, H.sc, kOpRho, P->stream, gate));
+      HIP_TRY(launch_pspmv_fin<R>(L, z, pc, pn, q, P->part, nb, H.sc, P->stream, gate));
+      HIP_TRY(launch_cg_update_fin<R>(x, r, pn, q, L.n, P->part, nb, H.sc, P->stream, gate));
+      std::swap(pc, pn);
     }
-    HIP_TRY(launch_dot<R>(r, z, L.n, P->part, nb, P->stream));
-    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpRho, P->stream));
-    HIP_TRY(launch_update_p<R>(z, p, L.n, H.sc, P->stream));
-    HIP_TRY(launch_spmv<R>(L, p, q, P->part, nb, P->stream));
-    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpPq, P->stream));
-    HIP_TRY(launch_cg_update<R>(x, r, p, q, L.n, H.sc, P->part, nb, P->stream));
-    HIP_TRY(launch_finish(P->part, nb, H.sc, kOpRr, P->stream));
-    P->iters[k]++;
     rc = read_scal(P, k);
     if (rc) return rc;
     // a stall (r.z or p.Ap <= 0 in finite precision) ends an inner level
     // quietly; on the finest level, and for non-finite values, it is a breakdown
     if (P->hsc->status < 0 || (P->hsc->status > 0 && k == 0)) {
       P->status = MSCG_E_BREAKDOWN;
-      fail(MSCG_E_BREAKDOWN, "level %d iteration %d: %s (rho %g, alpha %g, rr %g)", k, it + 1,
+      fail(MSCG_E_BREAKDOWN, "level %d iteration %d: %s (rho %g, alpha %g, rr %g)", k, P->hsc->started,
            P->hsc->status < 0 ? "non-finite reduction" : "r.z or p.Ap <= 0", P->hsc->rho, P->hsc->alpha, P->hsc->rr);
-      return MSCG_OK;
+      break;
     }
     if (P->hsc->status > 0 || P->hsc->converged) break;
     if (k == 0 && mixed(P)) P->tol_scale = P->hsc->rr > 0.0 ? 1.0 / P->hsc->rr : 1.0;
   }
+  P->iters[k] += P->hsc->started;
+  if (ahead) {
+    P->spec_hint[k] = P->hsc->started;
+    if (k + 1 == P->nlev - 1) P->calls[k + 1] += P->hsc->started;
+  }
   return MSCG_OK;
 }
 
-// Inner PCG on a large level k >= 1: rhs already in r_k, x_k = 0.
+// Inner PCG on a large level k >= 1: rhs already in r_k, x_k = 0.  The entry
+// check (with the mixed-precision floor) runs on the device; a queued-ahead
+// level does not wait for it, its iterations are gated on the result.
 int pcg_host(mscg_problem* P, int k) {
   LevelH& H = P->lev[k];
   const int nb = reduce_blocks(H.n);
@@ -385,25 +416,19 @@ int pcg_host(mscg_problem* P, int k) {
   if (rc) return rc;
   if (!mixed(P)) {
     HIP_TRY(launch_fill<double>(H.x, H.n, 0.0, P->stream));
-    HIP_TRY(launch_dot<double>(H.r, H.r, H.n, P->part, nb, P->stream));
+    HIP_TRY(launch_dot_fin<double>(H.r, H.r, H.n, P->part, nb, H.sc, kOpEntry, P->stream));
   } else {
     HIP_TRY(launch_fill<float>(H.x32, H.n, 0.0f, P->stream));
-    HIP_TRY(launch_dot<float>(H.r32, H.r32, H.n, P->part, nb, P->stream));
+    HIP_TRY(launch_dot_fin<float>(H.r32, H.r32, H.n, P->part, nb, H.sc, kOpEntry, P->stream));
   }
-  HIP_TRY(launch_finish(P->part, nb, H.sc, kOpEntry, P->stream));
-  rc = read_scal(P, k);
-  if (rc) return rc;
-  if (mixed(P) && P->o.inner_rel_floor > 0.0) {
-    const double floor2 = P->o.inner_rel_floor * P->o.inner_rel_floor * P->hsc->rr;
-    if (floor2 > level_tol(P, k) * P->tol_scale) {
-      rc = set_tol(P, k, floor2);
-      if (rc) return rc;
-      if (P->hsc->rr < floor2) return MSCG_OK;
-    }
+  const bool ahead = P->queue_ahead && (k + 1 == P->nlev - 1 || k + 1 >= P->ks);
+  if (!ahead) {
+    rc = read_scal(P, k);
+    if (rc) return rc;
+    if (P->hsc->converged) return MSCG_OK;
   }
-  if (P->hsc->converged) return MSCG_OK;
-  if (!mixed(P)) return cg_loop<double>(P, k, lv64(P, k), H.x, H.r, H.z, H.p, H.q, P->o.max_inner_iters);
-  return cg_loop<float>(P, k, lv32(P, k), H.x32, H.r32, H.z32, H.p32, H.q32, P->o.max_inner_iters);
+  if (!mixed(P)) return cg_loop<double>(P, k, lv64(P, k), H.x, H.r, H.z, H.p, H.p2, H.q, P->o.max_inner_iters);
+  return cg_loop<float>(P, k, lv32(P, k), H.x32, H.r32, H.z32, H.p32, H.p232, H.q32, P->o.max_inner_iters);
 }
 
 int carve(mscg_problem* P, const Plan& plan) {
@@ -425,14 +450,16 @@ int carve(mscg_problem* P, const Plan& plan) {
     L.tx = (double*)take(fx * 8); L.ty = (double*)take(fy * 8); L.tz = fz ? (double*)take(fz * 8) : nullptr;
     L.tx32 = L.ty32 = L.tz32 = nullptr;
     if (mx) { L.tx32 = (float*)take(fx * 4); L.ty32 = (float*)take(fy * 4); L.tz32 = fz ? (float*)take(fz * 4) : nullptr; }
-    L.x = L.r = L.z = L.p = L.q = L.w = nullptr;
-    L.x32 = L.r32 = L.z32 = L.p32 = L.q32 = L.w32 = nullptr;
+    L.x = L.r = L.z = L.p = L.q = L.w = L.p2 = nullptr;
+    L.x32 = L.r32 = L.z32 = L.p32 = L.q32 = L.w32 = L.p232 = nullptr;
     if (!mx || l == 0) {
       L.x = (double*)take((size_t)L.n * 8); L.r = (double*)take((size_t)L.n * 8); L.z = (double*)take((size_t)L.n * 8);
       L.p = (double*)take((size_t)L.n * 8); L.q = (double*)take((size_t)L.n * 8); L.w = (double*)take((size_t)L.n * 8);
+      L.p2 = (double*)take((size_t)L.n * 8);
     } else {
       L.x32 = (float*)take((size_t)L.n * 4); L.r32 = (float*)take((size_t)L.n * 4); L.z32 = (float*)take((size_t)L.n * 4);
       L.p32 = (float*)take((size_t)L.n * 4); L.q32 = (float*)take((size_t)L.n * 4); L.w32 = (float*)take((size_t)L.n * 4);
+      L.p232 = (float*)take((size_t)L.n * 4);
     }
     if (mx && l == 0) {
       L.r32 = (float*)take((size_t)L.n * 4);
@@ -565,6 +592,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
     P->tile_shape = t ? atoi(t) : -1;
     const char* v = getenv("MSCG_SMALL_VARIANT");
     P->small_variant = v ? atoi(v) : 0;
+    const char* qa = getenv("MSCG_QUEUE_AHEAD");
+    P->queue_ahead = !(qa && qa[0] == '0');
   }
   *out = P;
   return MSCG_OK;
@@ -692,7 +721,7 @@ static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_to
     P->calls[0]++;
     if (!P->hsc->converged) {
       if (mixed(P)) P->tol_scale = P->hsc->rr > 0.0 ? 1.0 / P->hsc->rr : 1.0;
-      rc = cg_loop<double>(P, 0, lv64(P, 0), p, L0.r, L0.z, L0.p, L0.q, P->o.max_outer_iters);
+      rc = cg_loop<double>(P, 0, lv64(P, 0), p, L0.r, L0.z, L0.p, L0.p2, L0.q, P->o.max_outer_iters);
       if (rc) return rc;
     }
     outer = (int)P->iters[0];
@@ -853,7 +882,7 @@ int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, doubl
   int rc = clear_scalars(P);
   if (rc) return rc;
   void* zres = nullptr;
-  rc = apply_prec(P, 0, &zres);
+  rc = apply_prec(P, 0, &zres, nullptr);
   if (rc) return rc;
   HIP_TRY(launch_copy<double>(static_cast<const double*>(zres), z, L0.n, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));

@@ -19,10 +19,13 @@ struct Scal {
   double alpha; // rho / (p . A p)
   double tol;   // absolute criterion on |r|^2: N_k f^k eps^2
   double zq;    // z_new . q_old (flexible beta)
+  double rel_floor2;  // mixed precision: the entry check raises tol to rel_floor2 |r|^2 (0 = off)
   int it;       // iterations done in the current call
-  int converged;
-  int status;   // 0 or -4 (breakdown)
+  int converged;  // also the gate of speculatively queued iterations: set, they do nothing
+  int status;   // 0, 1 (r.z or p.Ap <= 0) or -4 (non-finite)
   int flexible; // beta: 0 Fletcher-Reeves rho/rho_old, 1 Polak-Ribiere z.(r - r_old)/rho_old
+  int started;  // iterations begun in the current call (counted at r.z)
+  int pad_;
 };
 
 enum { kOpBB = 0, kOpEntry = 1, kOpRho = 2, kOpPq = 3, kOpRr = 4, kOpZq = 5 };
@@ -65,6 +68,7 @@ struct SmallDesc {
   long long *iters, *calls;
   int* status;
   int variant;  // one-workgroup kernel for 2-D levels: 0 colour-split, 1 cell-strided
+  const int* gate;  // see the gate of the grid-wide kernels
 };
 
 hipError_t launch_face_T(const FaceTArgs& a, hipStream_t s);
@@ -90,17 +94,35 @@ hipError_t launch_update_p(const R* z, R* p, int n, const Scal* sc, hipStream_t 
 template <typename R>
 hipError_t launch_cg_update(R* x, R* r, const R* p, const R* q, int n, const Scal* sc, double* part, int nparts,
                             hipStream_t s);
+// Kernels of an inner iteration take `gate`: when non-null and *gate != 0 (the
+// level has converged or stopped) they return at once, so iterations queued
+// ahead of the convergence test cost only their launch.
 template <typename R>
-hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s);
+hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s,
+                          const int* gate = nullptr);
 template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s);
 template <typename R>
 hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* tmp, R* g,
-                                    hipStream_t s);
+                                    hipStream_t s, const int* gate = nullptr);
 template <typename R>
-hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s);
+hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s, const int* gate = nullptr);
 template <typename R>
-hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s);
+hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s,
+                               const int* gate = nullptr);
+// A reduction kernel (gated) followed by its one-workgroup finish (gated),
+// which sums the partials in block order and updates sc with op.
+template <typename R>
+hipError_t launch_dot_fin(const R* a, const R* b, int n, double* part, int nparts, Scal* sc, int op, hipStream_t s,
+                          const int* gate = nullptr);
+// p_new = z (+ beta p_old), q = A p_new; finish: alpha = rho / p_new.q
+template <typename R>
+hipError_t launch_pspmv_fin(const Lv<R>& L, const R* z, const R* pold, R* pnew, R* q, double* part, int nparts,
+                            Scal* sc, hipStream_t s, const int* gate = nullptr);
+// x += alpha p, r -= alpha q; finish: rr = |r|^2 and the convergence test
+template <typename R>
+hipError_t launch_cg_update_fin(R* x, R* r, const R* p, const R* q, int n, double* part, int nparts, Scal* sc,
+                                hipStream_t s, const int* gate = nullptr);
 template <typename R>
 hipError_t launch_fill(R* a, long long n, R v, hipStream_t s);
 template <typename R>
@@ -126,7 +148,7 @@ hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s);
 bool smooth_tile_supported(int nz, bool has_tz, int m);
 template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, int m,
-                              int shape, hipStream_t s);
+                              int shape, hipStream_t s, const int* gate = nullptr);
 
 // Number of blocks (= partials) of a grid-wide reduction over n cells.
 inline int reduce_blocks(long long n) {

@@ -415,7 +415,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(Lv<R> L, const R* __restric
 // res = b - A x without a reduction
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_residual_nodot(Lv<R> L, const R* __restrict__ b, const R* __restrict__ x,
-                                                            R* __restrict__ res) {
+                                                            R* __restrict__ res, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
     int i, j, k;
     cell_ijk(c, L.nx, L.ny, i, j, k);
@@ -466,7 +467,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(R* __restrict__ x, R* __re
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gs_half(Lv<R> L, const R* __restrict__ r, R* __restrict__ x, int colour,
-                                                     int first) {
+                                                     int first, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   gs_half_range(L, r, x, colour, first != 0, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
@@ -478,19 +480,23 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Lv<R> F, Xfer X, const R* _
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_restrict_stored(Lv<R> F, Xfer X, const R* __restrict__ res,
-                                                             R* __restrict__ g) {
+                                                             R* __restrict__ g, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   restrict_stored_range(F, X, res, g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_prolong(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x) {
+__global__ void __launch_bounds__(kBlock) k_prolong(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate) return;
   prolong_range(F, X, y, x, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // y = A^-1 g on the coarsest level (dense FP64 inverse; g, y in R).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restrict__ Ainv, const R* __restrict__ g,
-                                                          R* __restrict__ y, int n) {
+                                                          R* __restrict__ y, int n, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
@@ -498,26 +504,24 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restric
   y[i] = (R)s;
 }
 
-// Scalar bookkeeping of one level's CG (Templates Figure 2.5), one workgroup.
-__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
-                                                   int op) {
-  __shared__ double sm[kBlock / kWave];
-  double acc = 0.0;
-  for (int q = threadIdx.x; q < nparts; q += blockDim.x) acc += part[q];
-  const double s = block_sum(acc, sm);
-  if (threadIdx.x != 0) return;
+// Scalar bookkeeping of one level's CG (Templates Figure 2.5) from the sum s
+// of a reduction; one thread.
+__device__ void apply_op(double s, Scal* __restrict__ sc, int op) {
   switch (op) {
     case kOpBB:
       sc->bb = s;
       break;
-    case kOpEntry:  // entry check of the level criterion
+    case kOpEntry:  // entry check of the level criterion, with the mixed-precision floor
       sc->rr = s;
       sc->it = 0;
+      sc->started = 0;
       sc->status = 0;
+      if (sc->rel_floor2 > 0.0 && sc->rel_floor2 * s > sc->tol) sc->tol = sc->rel_floor2 * s;
       sc->converged = s < sc->tol ? 1 : 0;
-      if (!(s == s) || s == INFINITY) sc->status = -4;
+      if (!(s == s) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
       break;
     case kOpRho:
+      sc->started += 1;
       // r.z <= 0 in finite precision: no further progress (status 1, the
       // caller decides); a non-finite value is a breakdown (-4)
       if (!(s == s) || s == INFINITY) { sc->status = -4; sc->converged = 1; }
@@ -543,7 +547,99 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ pa
   }
 }
 
-// b = f |V| + sum over Dirichlet boundary faces of T_b p_D (level 0).
+// Sum of the partials in block order (thread t takes partials t, t + blockDim,
+// ..., then the deterministic workgroup sum).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nparts, double* sm) {
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) acc += part[q];
+  return block_sum(acc, sm);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
+                                                   int op, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double sm[kBlock / kWave];
+  const double s = sum_partials(part, nparts, sm);
+  if (threadIdx.x == 0) apply_op(s, sc, op);
+}
+
+// partial sums of a . b (gated)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_dot_g(const R* __restrict__ a, const R* __restrict__ b, int n,
+                                                   double* __restrict__ part, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double sm[kBlock / kWave];
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    acc += (double)a[c] * (double)b[c];
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p_new = z (first iteration) or z + beta p_old, q = A p_new with partial
+// sums of p.q; the neighbours' p_new are formed from z and p_old on the fly
+// (p_new and p_old are different buffers).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pspmv(Lv<R> L, const R* __restrict__ z, const R* __restrict__ pold,
+                                                   R* __restrict__ pnew, R* __restrict__ q, double* __restrict__ part,
+                                                   const Scal* __restrict__ sc, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double sm[kBlock / kWave];
+  const bool first = sc->it == 0;
+  const R beta = (R)sc->beta;
+  auto pv = [&](int c) { return first ? z[c] : z[c] + beta * pold[c]; };
+  double acc = 0.0;
+  const int nx = L.nx, ny = L.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, nx, ny, i, j, k);
+    const int fx = i + (nx + 1) * (j + ny * k);
+    const int fy = i + nx * (j + (ny + 1) * k);
+    const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
+    R d = tw + te + ts + tn;
+    R o = R(0);
+    if (i > 0) o += tw * pv(c - 1);
+    if (i < nx - 1) o += te * pv(c + 1);
+    if (j > 0) o += ts * pv(c - nx);
+    if (j < ny - 1) o += tn * pv(c + nx);
+    if (L.tz) {
+      const int plane = nx * ny;
+      const int fz = i + nx * j + plane * k;
+      const R tb = L.tz[fz], tt = L.tz[fz + plane];
+      d += tb + tt;
+      if (k > 0) o += tb * pv(c - plane);
+      if (k < L.nz - 1) o += tt * pv(c + plane);
+    }
+    const R pc = pv(c);
+    const R v = d * pc - o;
+    pnew[c] = pc;
+    q[c] = v;
+    acc += (double)pc * (double)v;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q with partial sums of |r|^2 (gated)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cg_update_g(R* __restrict__ x, R* __restrict__ r,
+                                                         const R* __restrict__ p, const R* __restrict__ q, int n,
+                                                         double* __restrict__ part, const Scal* __restrict__ sc,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double sm[kBlock / kWave];
+  const R alpha = (R)sc->alpha;
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    x[c] += alpha * p[c];
+    const R v = r[c] - alpha * q[c];
+    r[c] = v;
+    acc += (double)v * (double)v;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 __global__ void k_rhs(RhsArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n) return;
@@ -623,10 +719,12 @@ struct SmallArgs {
   long long* iters;       // per level, accumulated (device)
   long long* calls;
   int* status;
+  const int* gate;
 };
 
 template <typename R>
 __global__ void __launch_bounds__(1024, 1) k_small_pcg(SmallArgs<R> args) {
+  if (args.gate && *args.gate) return;
   __shared__ double sm[1024 / kWave];
   __shared__ double sh_rho[kMaxLevels], sh_rr[kMaxLevels], sh_tol[kMaxLevels];
   __shared__ int sh_it[kMaxLevels];
@@ -888,9 +986,9 @@ hipError_t launch_cg_update(R* x, R* r, const R* p, const R* q, int n, const Sca
 }
 
 template <typename R>
-hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s) {
+hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s, const int* gate) {
   const long long tot = (long long)((L.nx + 1) / 2) * L.ny * L.nz;
-  hipLaunchKernelGGL(k_gs_half<R>, dim3(grid_for(tot, 1 << 20)), dim3(kBlock), 0, s, L, r, x, colour, first);
+  hipLaunchKernelGGL(k_gs_half<R>, dim3(grid_for(tot, 1 << 20)), dim3(kBlock), 0, s, L, r, x, colour, first, gate);
   return hipGetLastError();
 }
 
@@ -903,32 +1001,57 @@ hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x
 
 template <typename R>
 hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* tmp, R* g,
-                                    hipStream_t s) {
+                                    hipStream_t s, const int* gate) {
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
-  hipLaunchKernelGGL(k_residual_nodot<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, r, x, tmp);
+  hipLaunchKernelGGL(k_residual_nodot<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, r, x, tmp, gate);
   // one thread per coarse cell; small coarse grids use 64-thread blocks to spread over more CUs
   if (nc < 65536)
-    hipLaunchKernelGGL(k_restrict_stored<R>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, F, X, (const R*)tmp, g);
+    hipLaunchKernelGGL(k_restrict_stored<R>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, F, X, (const R*)tmp, g,
+                       gate);
   else
     hipLaunchKernelGGL(k_restrict_stored<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X,
-                       (const R*)tmp, g);
+                       (const R*)tmp, g, gate);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x);
+hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_solve<R>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Ainv, g, y, n);
+hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_coarse_solve<R>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Ainv, g, y, n, gate);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dot_fin(const R* a, const R* b, int n, double* part, int nparts, Scal* sc, int op, hipStream_t s,
+                          const int* gate) {
+  hipLaunchKernelGGL(k_dot_g<R>, dim3(nparts), dim3(kBlock), 0, s, a, b, n, part, gate);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, (const double*)part, nparts, sc, op, gate);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pspmv_fin(const Lv<R>& L, const R* z, const R* pold, R* pnew, R* q, double* part, int nparts,
+                            Scal* sc, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_pspmv<R>, dim3(nparts), dim3(kBlock), 0, s, L, z, pold, pnew, q, part, (const Scal*)sc, gate);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, (const double*)part, nparts, sc, (int)kOpPq, gate);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_cg_update_fin(R* x, R* r, const R* p, const R* q, int n, double* part, int nparts, Scal* sc,
+                                hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_cg_update_g<R>, dim3(nparts), dim3(kBlock), 0, s, x, r, p, q, n, part, (const Scal*)sc, gate);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, (const double*)part, nparts, sc, (int)kOpRr, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op, (const int*)nullptr);
   return hipGetLastError();
 }
 
@@ -988,6 +1111,7 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
   a.iters = d.iters;
   a.calls = d.calls;
   a.status = d.status;
+  a.gate = d.gate;
   // LDS plan: per level from the top small level down, faces then z then r;
   // then the coarsest level's rhs and solution; each array only if it fits.
   size_t off = 0;
@@ -1027,11 +1151,18 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
   template hipError_t launch_dot<R>(const R*, const R*, int, double*, int, hipStream_t);                          \
   template hipError_t launch_update_p<R>(const R*, R*, int, const Scal*, hipStream_t);                            \
   template hipError_t launch_cg_update<R>(R*, R*, const R*, const R*, int, const Scal*, double*, int, hipStream_t); \
-  template hipError_t launch_gs_half<R>(const Lv<R>&, const R*, R*, int, int, hipStream_t);                      \
+  template hipError_t launch_gs_half<R>(const Lv<R>&, const R*, R*, int, int, hipStream_t, const int*);          \
   template hipError_t launch_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, hipStream_t);         \
-  template hipError_t launch_residual_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, R*, hipStream_t); \
-  template hipError_t launch_prolong<R>(const Lv<R>&, const Xfer&, const R*, R*, hipStream_t);                    \
-  template hipError_t launch_coarse_solve<R>(const double*, const R*, R*, int, hipStream_t);                      \
+  template hipError_t launch_residual_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, R*, hipStream_t, \
+                                                  const int*);                                                     \
+  template hipError_t launch_prolong<R>(const Lv<R>&, const Xfer&, const R*, R*, hipStream_t, const int*);        \
+  template hipError_t launch_coarse_solve<R>(const double*, const R*, R*, int, hipStream_t, const int*);          \
+  template hipError_t launch_dot_fin<R>(const R*, const R*, int, double*, int, Scal*, int, hipStream_t,          \
+                                        const int*);                                                               \
+  template hipError_t launch_pspmv_fin<R>(const Lv<R>&, const R*, const R*, R*, R*, double*, int, Scal*,         \
+                                          hipStream_t, const int*);                                                \
+  template hipError_t launch_cg_update_fin<R>(R*, R*, const R*, const R*, int, double*, int, Scal*, hipStream_t, \
+                                              const int*);                                                         \
   template hipError_t launch_fill<R>(R*, long long, R, hipStream_t);                                              \
   template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);                                       \
   template hipError_t launch_small_pcg<R>(const SmallDesc<R>&, hipStream_t);

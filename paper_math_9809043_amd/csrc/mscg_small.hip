@@ -35,6 +35,7 @@ struct RegArgs {
   long long *iters, *calls;    // counters: [level] of the small level, [level + 1] of the coarsest
   int level;
   int* status;
+  const int* gate;
   // LDS layout (byte offsets)
   int off_z, off_p, off_x, off_res, off_tx, off_ty, off_g, off_y, off_part;
 };
@@ -53,6 +54,7 @@ __device__ __forceinline__ double wsum_block(double v, double* sm) {
 
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kThreads, 1) k_small_reg(RegArgs a) {
+  if (a.gate && *a.gate) return;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ double sm[kThreads / kWave];
   R* z = reinterpret_cast<R*>(lds + a.off_z);
@@ -324,6 +326,7 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
   a.rhs = d.r[ks]; a.x = d.x[ks];
   a.Ainv = d.Ainv;
   a.iters = d.iters; a.calls = d.calls; a.level = ks; a.status = d.status;
+  a.gate = d.gate;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const int o = (int)off;

@@ -57,12 +57,14 @@ struct Small2dArgs {
   long long *iters, *calls;
   int level;
   int* status;
+  const int* gate;
   int pitch;                    // entries per colour in the padded arrays: kSlots + 2 H
   int off_z, off_p, off_res, off_tx1, off_g, off_y, off_part, off_wx, off_wy, off_ci, off_cw, off_ri, off_rw;
 };
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
+  if (a.gate && *a.gate) return;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ __align__(16) double sm[2][kThreads2 / kWave];
   R* z = reinterpret_cast<R*>(lds + a.off_z);
@@ -342,6 +344,7 @@ hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s) {
   a.tx = V.tx; a.ty = V.ty; a.rhs = d.r[ks]; a.x = d.x[ks];
   a.Ainv = d.Ainv;
   a.iters = d.iters; a.calls = d.calls; a.level = ks; a.status = d.status;
+  a.gate = d.gate;
   a.pitch = kSlots + 2 * H;
   size_t off = 0;
   auto take = [&](size_t bytes) {

@@ -30,7 +30,8 @@ constexpr int kHalo = 9;  // 2m + 1 for m = 4
 template <typename R, bool POST, int TW, int TH, int BX, int BY>
 __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                          const R* __restrict__ zin, const R* __restrict__ y,
-                                                         R* __restrict__ zout) {
+                                                         R* __restrict__ zout, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   constexpr int MW = TW + 2 * kHalo, MH = TH + 2 * kHalo;
   constexpr int HW = (MW + 1) / 2;         // cells of one colour per region row, upper bound
   constexpr int NR = (MH + BY - 1) / BY;   // region rows per thread
@@ -136,13 +137,15 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
 }
 
 template <typename R, int TW, int TH, int BX, int BY>
-hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, hipStream_t s) {
+hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, hipStream_t s,
+                        const int* gate) {
   const dim3 grid((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
   const dim3 block(BX * BY);
   if (X)
-    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout);
+    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout, gate);
   else
-    hipLaunchKernelGGL((k_smooth_tile<R, false, TW, TH, BX, BY>), grid, block, 0, s, L, Xfer{}, r, zin, y, zout);
+    hipLaunchKernelGGL((k_smooth_tile<R, false, TW, TH, BX, BY>), grid, block, 0, s, L, Xfer{}, r, zin, y, zout,
+                       gate);
   return hipGetLastError();
 }
 
@@ -163,20 +166,20 @@ bool smooth_tile_supported(int nz, bool has_tz, int m) { return nz == 1 && !has_
 
 template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout,
-                              int m, int shape, hipStream_t s) {
+                              int m, int shape, hipStream_t s, const int* gate) {
   if (!smooth_tile_supported(L.nz, L.tz != nullptr, m)) return hipErrorNotSupported;
   if (shape < 0 || shape > 3) shape = auto_shape(L.nx, L.ny);
   switch (shape) {
-    case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s);
-    case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s);
-    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s);
-    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s);
+    case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate);
+    case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate);
+    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s, gate);
+    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate);
   }
 }
 
 template hipError_t launch_smooth_tile<double>(const Lv<double>&, const Xfer*, const double*, const double*,
-                                               const double*, double*, int, int, hipStream_t);
+                                               const double*, double*, int, int, hipStream_t, const int*);
 template hipError_t launch_smooth_tile<float>(const Lv<float>&, const Xfer*, const float*, const float*,
-                                              const float*, float*, int, int, hipStream_t);
+                                              const float*, float*, int, int, hipStream_t, const int*);
 
 }  // namespace mscg
