@@ -195,6 +195,23 @@ enum {
  * mscg_set_permeability; run a solve first so the vectors hold finite values. */
 int mscg_time_kernel(mscg_problem *prob, int kernel, int level, int reps, double *avg_us, double *alg_bytes);
 
+/* Launch timing of the one-workgroup solver of the last inner level (the
+ * inner PCG of the level above the coarsest grid, Section 2.3, with its
+ * coarsest solve), available for 2-D hierarchies of three or more levels
+ * whose last inner level runs in one workgroup (MSCG_E_ARG otherwise).
+ * on = 1 clears the totals and brackets each of its launches in the following
+ * solves with HIP events on the problem's stream; on = 0 stops recording. */
+int mscg_enable_kernel_timing(mscg_problem *prob, int on);
+
+/* Totals since timing was enabled: summed launch durations (ms, HIP events),
+ * launches (every dispatch, including those of iterations queued past
+ * convergence, which return at once), iterations of that level, and their
+ * algorithmic FP64 operations: per iteration (9 (2m+1) + 45) n + 4 ny ncx +
+ * 2 nc^2 for a level of n cells (ny rows) above a coarsest level of nc cells
+ * (ncx columns).  Any pointer may be NULL. */
+int mscg_small_level_timing(const mscg_problem *prob, double *total_ms, long long *launches, long long *iterations,
+                            double *flops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -156,6 +156,12 @@ struct mscg_problem {
   int* dflags;        // [0] coarse factor status, [1] bad K, [2] small-kernel status
   int spec_hint[MSCG_MAX_LEVELS];  // iterations of the level's last call: how many to queue ahead
   bool queue_ahead;   // queue inner iterations ahead of their convergence test
+  // launch timing of the one-workgroup solver of the last inner level
+  bool ktime;
+  std::vector<hipEvent_t> kev;  // event pairs around its launches, reused
+  size_t kev_used;
+  double ktime_ms, kflops;
+  long long klaunches, kiters;
   long long* dcount;  // [0..7] small iters, [8..15] small calls
   Scal* hsc;          // pinned mirror of one Scal
   int* hflags;        // pinned
@@ -228,6 +234,31 @@ int set_tol(mscg_problem* P, int k, double tol) {
 
 int pcg_host(mscg_problem* P, int k);
 
+// Next event of the launch-timing pool (created on first use, kept until the
+// problem is destroyed).
+hipEvent_t timing_event(mscg_problem* P) {
+  if (P->kev_used == P->kev.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P->kev.push_back(e);
+  }
+  return P->kev[P->kev_used++];
+}
+
+// Algorithmic FP64 operations of one iteration of the one-workgroup solver on
+// a 2-D level of n cells (nx x ny) above a coarsest level of nc cells (ncx
+// wide): 2m+1 half sweeps before and after (9 per cell update: four products,
+// four sums, one division), residual (10 n), restriction (4 n + 4 ny ncx),
+// dense coarsest solve (2 nc^2), prolongation (10 n), CG vectors (21 n).
+double small_level_flops(const mscg_problem* P) {
+  const int ks = P->nlev - 2;
+  if (ks < 0) return 0.0;
+  const LevelH& S = P->lev[ks];
+  const LevelH& C = P->lev[ks + 1];
+  const double n = S.n, nc = C.n, m = P->o.smooth_steps;
+  return (9.0 * (2.0 * m + 1.0) + 45.0) * n + 4.0 * S.ny * S.nz * C.nx + 2.0 * nc * nc;
+}
+
 // Coarse part of the preconditioner on level k: y_{k+1} = A_{k+1}^-1 g.
 template <typename R>
 int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* const* zs, R* const* ps, R* const* qs,
@@ -262,9 +293,11 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
     d.status = P->dflags + 2;
     d.variant = P->small_variant;
     d.gate = gate;
+    if (P->ktime) HIP_TRY(hipEventRecord(timing_event(P), P->stream));
     const hipError_t e = launch_small_reg<R>(d, P->stream);
     if (e == hipErrorNotSupported) HIP_TRY(launch_small_pcg<R>(d, P->stream));
     else HIP_TRY(e);
+    if (P->ktime) HIP_TRY(hipEventRecord(timing_event(P), P->stream));
     return MSCG_OK;
   }
   return pcg_host(P, kc);
@@ -601,6 +634,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
 
 int mscg_destroy_problem(mscg_problem* P) {
   if (!P) return MSCG_OK;
+  for (hipEvent_t e : P->kev)
+    if (e) (void)hipEventDestroy(e);
   if (P->owns_ws && P->ws) (void)hipFree(P->ws);
   if (P->hsc) (void)hipHostFree(P->hsc);
   if (P->hflags) (void)hipHostFree(P->hflags);
@@ -736,6 +771,19 @@ static int solve_impl(mscg_problem* P, const double* f, double* p, double rel_to
   if (rc) return rc;
   const double rt = P->hsc->bb;
   auto t1 = std::chrono::steady_clock::now();
+  if (P->ktime) {
+    for (size_t q = 0; q + 1 < P->kev_used; q += 2) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, P->kev[q], P->kev[q + 1]));
+      P->ktime_ms += ms;
+      P->klaunches += 1;
+    }
+    P->kev_used = 0;
+    if (P->ks == P->nlev - 2) {
+      P->kiters += P->hcount[P->ks];
+      P->kflops += small_level_flops(P) * (double)P->hcount[P->ks];
+    }
+  }
   int status = P->status;
   if (P->hflags[2]) {
     status = MSCG_E_BREAKDOWN;
@@ -887,6 +935,29 @@ int mscg_apply_preconditioner(mscg_problem* P, const double* r, double* z, doubl
   HIP_TRY(launch_copy<double>(static_cast<const double*>(zres), z, L0.n, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return P->status;
+}
+
+int mscg_enable_kernel_timing(mscg_problem* P, int on) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (P->ks != P->nlev - 2 || P->nlev < 3 || P->g.dim != 2)
+    return fail(MSCG_E_ARG, "no one-workgroup solver of a 2-D last inner level in this hierarchy");
+  P->ktime = on != 0;
+  P->kev_used = 0;
+  P->ktime_ms = P->kflops = 0.0;
+  P->klaunches = P->kiters = 0;
+  return MSCG_OK;
+}
+
+int mscg_small_level_timing(const mscg_problem* P, double* total_ms, long long* launches, long long* iterations,
+                            double* flops) {
+  g_err.clear();
+  if (!P) return fail(MSCG_E_ARG, "problem is NULL");
+  if (total_ms) *total_ms = P->ktime_ms;
+  if (launches) *launches = P->klaunches;
+  if (iterations) *iterations = P->kiters;
+  if (flops) *flops = P->kflops;
+  return MSCG_OK;
 }
 
 int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* avg_us, double* alg_bytes) {

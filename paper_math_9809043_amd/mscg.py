@@ -53,7 +53,7 @@ EXPORTS = [
     "mscg_default_options", "mscg_footprint_bytes", "mscg_create_problem", "mscg_set_permeability", "mscg_solve",
     "mscg_solve_batch", "mscg_destroy_problem", "mscg_last_error", "mscg_level_info", "mscg_get_transmissibility",
     "mscg_apply_operator", "mscg_apply_smoother", "mscg_restrict_residual", "mscg_prolong_add",
-    "mscg_apply_preconditioner", "mscg_time_kernel",
+    "mscg_apply_preconditioner", "mscg_time_kernel", "mscg_enable_kernel_timing", "mscg_small_level_timing",
 ]
 (KERNEL_SMOOTH_HALF, KERNEL_SPMV, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_CG_UPDATE, KERNEL_SMOOTH_PRE,
  KERNEL_SMOOTH_POST) = range(7)
@@ -104,6 +104,11 @@ def load_library(path: str = LIB_PATH):
     L.mscg_apply_preconditioner.restype = ctypes.c_int
     L.mscg_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
     L.mscg_time_kernel.restype = ctypes.c_int
+    L.mscg_enable_kernel_timing.argtypes = [vp, ctypes.c_int]
+    L.mscg_enable_kernel_timing.restype = ctypes.c_int
+    L.mscg_small_level_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                          dp]
+    L.mscg_small_level_timing.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -295,6 +300,19 @@ class Problem:
         us, b = ctypes.c_double(), ctypes.c_double()
         _check(self._L.mscg_time_kernel(self._h, kernel, level, reps, ctypes.byref(us), ctypes.byref(b)))
         return us.value, b.value
+
+    def enable_kernel_timing(self, on: bool = True):
+        """Brackets each launch of the one-workgroup last-inner-level solver with
+        HIP events in the following solves (clears the totals)."""
+        _check(self._L.mscg_enable_kernel_timing(self._h, 1 if on else 0))
+
+    def small_level_timing(self) -> dict:
+        """Totals since enable_kernel_timing: ms, launches, iterations, FP64 flops."""
+        ms, fl = ctypes.c_double(), ctypes.c_double()
+        nl, it = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(self._L.mscg_small_level_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(it),
+                                               ctypes.byref(fl)))
+        return {"total_ms": ms.value, "launches": nl.value, "iterations": it.value, "flops": fl.value}
 
     def apply_preconditioner(self, r, z, eps2: float = 0.0):
         _check(self._L.mscg_apply_preconditioner(self._h, _f64(r), _f64(z), float(eps2)), allow=(OK, E_BREAKDOWN))
