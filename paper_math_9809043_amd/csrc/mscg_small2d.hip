@@ -19,13 +19,14 @@
 // diagonal: they stay zero.
 //
 // Per owned cell the thread keeps its four neighbour coefficients (zero
-// across the boundary), diagonal, residual r and iterate x in registers.  The
+// across the boundary), diagonal and its inverse, residual r and iterate x in
+// registers.  The
 // restriction E^T runs as an x pass over (fine row, coarse column) and a y
 // pass over (coarse row, coarse column), each output with its footprint
 // weights tabulated in LDS once per launch; the prolongation E reads the
 // per-column and per-row extension weights from LDS tables.  The coarsest
-// solve is the dense FP64 inverse applied by the whole workgroup, its rows
-// loaded in batches of 8.  Reductions: DPP within each wave, then the 16
+// solve is the dense FP64 inverse applied by the whole workgroup, each lane
+// reading two adjacent entries of a row at once, eight rows in flight.  Reductions: DPP within each wave, then the 16
 // wave sums in order, so every result is independent of scheduling.
 #include <hip/hip_runtime.h>
 
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
     jv[v] = q / H;
     mv[v] = q - jv[v] * H;
   }
-  R ccw[kU], cce[kU], ccs[kU], ccn[kU], dg[kU], r[kU], x[kU];
+  R ccw[kU], cce[kU], ccs[kU], ccn[kU], dg[kU], di[kU], r[kU], x[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
     const int cl = u / kV, v = u % kV;
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
     const int fx = ii + (nx + 1) * jj, fy = ii + nx * jj;
     const R tw = TX[fx], te = TX[fx + 1], ts = TY[fy], tn = TY[fy + nx];
     dg[u] = ok ? tw + te + ts + tn : R(1);
+    di[u] = R(1) / dg[u];
     ccw[u] = ok && ii > 0 ? tw : R(0);
     cce[u] = ok && ii < nx - 1 ? te : R(0);
     ccs[u] = ok && jj > 0 ? ts : R(0);
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (u / kV != cl) continue;
-      z[own_at(u)] = first ? r[u] / dg[u] : (r[u] + offsum(z, u)) / dg[u];
+      z[own_at(u)] = first ? r[u] * di[u] : (r[u] + offsum(z, u)) * di[u];
     }
     __syncthreads();
   };
@@ -195,7 +197,8 @@ __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
   long long iters = 0, coarse_calls = 0;
   int status = 0;
   double rho_old = 0.0;
-  const int groups = nc >= kThreads2 ? 1 : kThreads2 / nc;
+  const int half_nc = nc / 2;  // nc is even (checked at launch)
+  const int groups = kThreads2 / half_nc;
   const int per = (nc + groups - 1) / groups;
 
   if (!(rr < tol)) {
@@ -232,20 +235,28 @@ __global__ void __launch_bounds__(kThreads2, 1) k_small_2d(Small2dArgs a) {
         g[e] = (double)s;
       }
       __syncthreads();
-      // -- coarsest: y = A^-1 g; thread (group, i) sums its column range in order
-      if (tid < groups * nc) {
-        const int i = tid % nc, grp = tid / nc;
+      // -- coarsest: y = A^-1 g.  Thread (group, pair) sums two adjacent outputs over
+      // its column range in order, reading 16 bytes per row; the group partials
+      // are then summed in group order.
+      if (tid < groups * half_nc) {
+        const int ip = tid % half_nc, grp = tid / half_nc;
         const int j0 = grp * per, j1 = min(j0 + per, nc);
-        double s = 0.0;
+        double s0 = 0.0, s1 = 0.0;
         for (int jb = j0; jb < j1; jb += kBatch) {
-          double av[kBatch];
-#pragma unroll
-          for (int t = 0; t < kBatch; ++t) av[t] = jb + t < j1 ? a.Ainv[(long long)(jb + t) * nc + i] : 0.0;
+          double2 av[kBatch];
 #pragma unroll
           for (int t = 0; t < kBatch; ++t)
-            if (jb + t < j1) s += av[t] * g[jb + t];
+            av[t] = jb + t < j1 ? *reinterpret_cast<const double2*>(a.Ainv + (long long)(jb + t) * nc + 2 * ip)
+                              : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int t = 0; t < kBatch; ++t)
+            if (jb + t < j1) {
+              s0 += av[t].x * g[jb + t];
+              s1 += av[t].y * g[jb + t];
+            }
         }
-        part[grp * nc + i] = s;
+        part[grp * nc + 2 * ip] = s0;
+        part[grp * nc + 2 * ip + 1] = s1;
       }
       __syncthreads();
       for (int i = tid; i < nc; i += kThreads2) {
@@ -332,7 +343,7 @@ hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s) {
   if (V.tz || V.nz != 1 || S > kSlots) return hipErrorNotSupported;
   if (V.nx >= (1 << 15) || V.ny >= (1 << 15) || X.cnx >= (1 << 15) || X.cny >= (1 << 15)) return hipErrorNotSupported;
   const int nc = X.cnx * X.cny;
-  if (nc > kThreads2) return hipErrorNotSupported;
+  if (nc > kThreads2 || nc % 2) return hipErrorNotSupported;  // the coarsest product reads output pairs
   // footprints must fit the tables: s + 2 (s / 2) + 2 fine cells (linear), s (constant)
   auto foot = [&](int f) { return f == 1 ? 1 : X.interp == 1 ? f : f + 2 * (f / 2) + 2; };
   if (foot(X.sx) > kFoot || foot(X.sy) > kFoot) return hipErrorNotSupported;
@@ -358,7 +369,7 @@ hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s) {
   a.off_tx1 = take((size_t)V.ny * X.cnx * sizeof(R));
   a.off_g = take((size_t)nc * sizeof(double));
   a.off_y = take((size_t)nc * sizeof(double));
-  a.off_part = take((size_t)kThreads2 * sizeof(double));
+  a.off_part = take((size_t)2 * kThreads2 * sizeof(double));
   a.off_wx = take((size_t)X.cnx * kFoot * sizeof(R));
   a.off_wy = take((size_t)X.cny * kFoot * sizeof(R));
   a.off_ci = take((size_t)V.nx * sizeof(int));
