@@ -326,7 +326,16 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
     for (int h = 0; h <= 2 * m; ++h)
       if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream, gate))) return nullptr;
   }
-  if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream, gate))) return nullptr;
+  if (tiled) {
+    const hipError_t e = launch_resid_restrict_tile<R>(L, X, r, z, rs[k + 1], P->stream, gate);
+    if (e == hipErrorNotSupported) {
+      if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream, gate))) return nullptr;
+    } else if (!chk(e)) {
+      return nullptr;
+    }
+  } else if (!chk(launch_residual_restrict<R>(L, X, r, z, w, rs[k + 1], P->stream, gate))) {
+    return nullptr;
+  }
   *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs, gate);
   if (*rc) return nullptr;
   if (tiled) {

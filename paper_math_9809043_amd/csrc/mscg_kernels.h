@@ -150,6 +150,14 @@ template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, int m,
                               int shape, hipStream_t s, const int* gate = nullptr);
 
+// g = E^T (r - A z) on a 2-D level in one launch (factors s <= 4 per axis);
+// hipErrorNotSupported otherwise.  Same sums, in the same order, as
+// launch_residual_restrict.
+bool resid_restrict_tile_supported(const Lv<double>& L, const Xfer& X);
+template <typename R>
+hipError_t launch_resid_restrict_tile(const Lv<R>& L, const Xfer& X, const R* r, const R* z, R* g, hipStream_t s,
+                                      const int* gate = nullptr);
+
 // Number of blocks (= partials) of a grid-wide reduction over n cells.
 inline int reduce_blocks(long long n) {
   long long b = (n + 255) / 256;

@@ -160,6 +160,82 @@ int auto_shape(int nx, int ny) {
   return cells >= (1LL << 19) ? 2 : 3;
 }
 
+// Residual and restriction in one pass (2-D): g = E^T (r - A z), Section 3.
+// A workgroup owns kCTx x kCTy coarse cells.  It loads the fine cells of their
+// footprint (plus a one-cell halo of z) into LDS, forms the residual there,
+// then sums each fine row against the x weights of each coarse column and
+// those row sums against the y weights.  Terms and order are those of the
+// two-kernel path (residual stored, then the stored-residual restriction), so
+// the result is the same bit for bit.
+constexpr int kCTx = 8, kCTy = 4;          // coarse cells per workgroup
+constexpr int kFootMax = 4 * 1 + 2 * 2 + 2;  // fine cells in one coarse cell's footprint for s <= 4
+constexpr int kRegW = 4 * (kCTx - 1) + kFootMax, kRegH = 4 * (kCTy - 1) + kFootMax;
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_resid_restrict_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
+                                                             const R* __restrict__ z, R* __restrict__ g,
+                                                             const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ R zs[kRegH + 2][kRegW + 2];
+  __shared__ R res[kRegH][kRegW];
+  __shared__ R tmp[kRegH][kCTx];
+  const int nx = L.nx, ny = L.ny, tid = threadIdx.x;
+  const int I0 = blockIdx.x * kCTx, J0 = blockIdx.y * kCTy;
+  const int I1 = min(I0 + kCTx, X.cnx) - 1, J1 = min(J0 + kCTy, X.cny) - 1;
+  int lox, hix, loy, hiy, t0, t1;
+  ext_support(I0, X.sx, nx, X.interp, lox, t0);
+  ext_support(I1, X.sx, nx, X.interp, t1, hix);
+  ext_support(J0, X.sy, ny, X.interp, loy, t0);
+  ext_support(J1, X.sy, ny, X.interp, t1, hiy);
+  const int RW = hix - lox + 1, RH = hiy - loy + 1;
+  // z on the region and a one-cell ring (zero outside the grid: those terms are skipped)
+  for (int e = tid; e < (RH + 2) * (RW + 2); e += blockDim.x) {
+    const int lj = e / (RW + 2), li = e - lj * (RW + 2);
+    const int i = lox - 1 + li, j = loy - 1 + lj;
+    zs[lj][li] = (i >= 0 && i < nx && j >= 0 && j < ny) ? z[i + nx * j] : R(0);
+  }
+  __syncthreads();
+  for (int e = tid; e < RH * RW; e += blockDim.x) {
+    const int lj = e / RW, li = e - lj * RW;
+    const int i = lox + li, j = loy + lj;
+    const int fx = i + (nx + 1) * j, fy = i + nx * j;
+    const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
+    const R d = tw + te + ts + tn;
+    R o = R(0);
+    if (i > 0) o += tw * zs[lj + 1][li];
+    if (i < nx - 1) o += te * zs[lj + 1][li + 2];
+    if (j > 0) o += ts * zs[lj][li + 1];
+    if (j < ny - 1) o += tn * zs[lj + 2][li + 1];
+    res[lj][li] = r[fy] - (d * zs[lj + 1][li + 1] - o);
+  }
+  __syncthreads();
+  // x pass: row lj against the weights of coarse column I over its footprint
+  for (int e = tid; e < RH * kCTx; e += blockDim.x) {
+    const int lj = e / kCTx, I = I0 + (e - lj * kCTx);
+    if (I > I1) continue;
+    int ilo, ihi;
+    ext_support(I, X.sx, nx, X.interp, ilo, ihi);
+    R racc = R(0);
+    for (int i = ilo; i <= ihi; ++i) racc += ext_weight_of<R>(i, I, X.sx, X.cnx, X.interp) * res[lj][i - lox];
+    tmp[lj][e - lj * kCTx] = racc;
+  }
+  __syncthreads();
+  // y pass
+  for (int e = tid; e < kCTy * kCTx; e += blockDim.x) {
+    const int J = J0 + e / kCTx, I = I0 + e % kCTx;
+    if (J > J1 || I > I1) continue;
+    int jlo, jhi;
+    ext_support(J, X.sy, ny, X.interp, jlo, jhi);
+    R acc = R(0);
+    for (int j = jlo; j <= jhi; ++j) {
+      const R wj = ext_weight_of<R>(j, J, X.sy, X.cny, X.interp);
+      if (wj == R(0)) continue;
+      acc += (R(1) * wj) * tmp[j - loy][e % kCTx];
+    }
+    g[I + X.cnx * J] = acc;
+  }
+}
+
 }  // namespace
 
 bool smooth_tile_supported(int nz, bool has_tz, int m) { return nz == 1 && !has_tz && 2 * m + 1 == kHalo; }
@@ -176,6 +252,26 @@ hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R
     default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate);
   }
 }
+
+bool resid_restrict_tile_supported(const Lv<double>& L, const Xfer& X) {
+  auto ok = [&](int f) { return f >= 1 && f <= 4; };
+  return !L.tz && L.nz == 1 && X.cnz == 1 && ok(X.sx) && ok(X.sy);
+}
+
+template <typename R>
+hipError_t launch_resid_restrict_tile(const Lv<R>& L, const Xfer& X, const R* r, const R* z, R* g, hipStream_t s,
+                                      const int* gate) {
+  const Lv<double> shape{L.nx, L.ny, L.nz, L.n, nullptr, nullptr, L.tz ? (const double*)1 : nullptr};
+  if (!resid_restrict_tile_supported(shape, X)) return hipErrorNotSupported;
+  const dim3 grid((X.cnx + kCTx - 1) / kCTx, (X.cny + kCTy - 1) / kCTy);
+  hipLaunchKernelGGL(k_resid_restrict_tile<R>, grid, dim3(256), 0, s, L, X, r, z, g, gate);
+  return hipGetLastError();
+}
+
+template hipError_t launch_resid_restrict_tile<double>(const Lv<double>&, const Xfer&, const double*, const double*,
+                                                      double*, hipStream_t, const int*);
+template hipError_t launch_resid_restrict_tile<float>(const Lv<float>&, const Xfer&, const float*, const float*,
+                                                     float*, hipStream_t, const int*);
 
 template hipError_t launch_smooth_tile<double>(const Lv<double>&, const Xfer*, const double*, const double*,
                                                const double*, double*, int, int, hipStream_t, const int*);
