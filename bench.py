@@ -29,7 +29,12 @@ WORKLOADS = {
                        make="smooth", opt={}),
     "layered128": dict(desc="3-D 7-point FV, 128^3 (2,097,152 unknowns); 16 layers of log10 kx = log10 ky ~ "
                             "U[-3,3], kz = kx/100; Dirichlet on the x faces; f ~ N(0,1); tol 1e-10; "
-                            "piecewise-constant extension", make="layered", opt={"interp": 1}),
+                            "aspect-ratio-aware plan with axis weights (1, 1, 0.01): levels 128^3, 32x32x128, "
+                            "8x8x128, 8x8x32, 8^3; piecewise-constant extension", make="layered",
+                       opt={"semi_coarsen": 1, "axis_weight": (1.0, 1.0, 0.01), "interp": 1}),
+    "layered128_uniform": dict(desc="the same 128^3 layered problem with every axis coarsened together (128^3, "
+                                    "32^3, 8^3) and piecewise-constant extension", make="layered",
+                               opt={"interp": 1}),
     "channel1024": dict(desc="2-D, 1024x1024, 8x8-cell blocks of log10 k ~ U[-4.5,4.5] plus 5 channels "
                              "(contrast 1e9); tol 1e-10; piecewise-constant extension", make="channel",
                         opt={"interp": 1}),
@@ -220,20 +225,22 @@ def main():
         serving = run_serving(args.serve_requests)
 
     extra = {}
-    if not args.no_3d and args.workload != "layered128":
-        W3 = WORKLOADS["layered128"]
-        P3 = make_problem(W3["make"])
-        _, st3, wall3, solve3, _ = run_gpu(P3, W3["opt"], 2, 1)
-        opt3 = dict(W3["opt"])
-        opt3["precision"] = mscg.MIXED
-        _, st3m, wall3m, solve3m, _ = run_gpu(P3, opt3, 2, 1)
-        extra["layered128"] = {"workload": W3["desc"], "fp64": {"value": round(P3.N / (wall3 * 1e-3), 1),
-                               "ms_per_step": round(wall3, 3), "outer_iters": st3.outer_iters,
-                               "level_iters": st3.level_iters, "rel_residual_true": st3.rel_residual_true},
-                               "mixed": {"value": round(P3.N / (wall3m * 1e-3), 1), "ms_per_step": round(wall3m, 3),
-                                         "outer_iters": st3m.outer_iters,
-                                         "rel_residual_true": st3m.rel_residual_true}}
-        print(f"[bench] layered128: fp64 {wall3:.1f} ms, mixed {wall3m:.1f} ms", flush=True)
+    if not args.no_3d and not args.workload.startswith("layered128"):
+        P3 = make_problem("layered")
+        for key in ("layered128", "layered128_uniform"):
+            W3 = WORKLOADS[key]
+            _, st3, wall3, solve3, _ = run_gpu(P3, W3["opt"], 2, 1)
+            opt3 = dict(W3["opt"])
+            opt3["precision"] = mscg.MIXED
+            _, st3m, wall3m, solve3m, _ = run_gpu(P3, opt3, 2, 1)
+            extra[key] = {"workload": W3["desc"], "fp64": {"value": round(P3.N / (wall3 * 1e-3), 1),
+                          "ms_per_step": round(wall3, 3), "outer_iters": st3.outer_iters,
+                          "level_iters": st3.level_iters, "rel_residual_true": st3.rel_residual_true},
+                          "mixed": {"value": round(P3.N / (wall3m * 1e-3), 1), "ms_per_step": round(wall3m, 3),
+                                    "outer_iters": st3m.outer_iters, "level_iters": st3m.level_iters,
+                                    "rel_residual_true": st3m.rel_residual_true}}
+            print(f"[bench] {key}: fp64 {wall3:.1f} ms (outer {st3.outer_iters}, levels {st3.level_iters}), "
+                  f"mixed {wall3m:.1f} ms (outer {st3m.outer_iters})", flush=True)
 
     value = P.N / (wall_ms * 1e-3)
     line = {

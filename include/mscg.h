@@ -84,6 +84,11 @@ typedef struct {
   int flexible;           /* beta on the host-driven levels: 0 Fletcher-Reeves (Templates CG, default),
                              1 Polak-Ribiere, robust to a preconditioner that varies between iterations */
   double inner_rel_floor; /* MIXED only: inner levels stop once |r| <= floor * |rhs| (default 1e-6) */
+  int semi_coarsen;       /* 0: every axis coarsened together (default).  1: aspect-ratio-aware plan
+                             (Section 5, anisotropic strip): per level, among the axes that can be
+                             coarsened by `scale`, those whose effective cell size h_a / sqrt(axis_weight[a])
+                             is within sqrt(scale) of the smallest are coarsened */
+  double axis_weight[3];  /* permeability scale per axis for that plan (e.g. 1, 1, kz/kx), default 1 */
 } mscg_options;
 
 typedef struct {

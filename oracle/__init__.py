@@ -56,10 +56,12 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_solve.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp, dp, ip, dp, ctypes.c_double, ip, dp, dp,
-                                   ctypes.POINTER(_Stats)]
+                                   ctypes.POINTER(_Stats), dp]
         L.oracle_solve.restype = ctypes.c_int
         L.oracle_level_plan.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
         L.oracle_level_plan.restype = ctypes.c_int
+        L.oracle_level_plan_semi.argtypes = [ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
+        L.oracle_level_plan_semi.restype = ctypes.c_int
         L.oracle_face_T.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 3 + [dp, dp, dp, ip, dp, dp, dp]
         L.oracle_face_T.restype = None
         L.oracle_coarsen_T.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp, dp, dp, dp]
@@ -79,10 +81,10 @@ def lib():
         L.oracle_cholesky_solve.argtypes = [ctypes.c_int, dp, dp, dp]
         L.oracle_cholesky_solve.restype = None
         L.oracle_precond.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp, ip, ip, ctypes.c_double, ctypes.c_double,
-                                     dp, dp]
+                                     dp, dp, dp]
         L.oracle_precond.restype = ctypes.c_int
         L.oracle_hierarchy_T.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, dp, ctypes.c_size_t]
+                                         ctypes.c_int, dp, ctypes.c_size_t, dp]
         L.oracle_hierarchy_T.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,9 +127,16 @@ def _opts(scale=4, min_side=8, m=0, max_outer=200, max_inner=200, max_levels=MAX
     return [scale, min_side, m, max_outer, max_inner, max_levels, interp]
 
 
-def solve_arrays(dim, n, kx, ky, kz, f, bc_type, bc_value, tol, length=(1.0, 1.0, 1.0), flvl=0.1, **opt) -> Result:
-    """Solve -div(K grad p) = f with the oracle's recursive multi-scale PCG."""
+def _axis_w(axis_weight):
+    return None if axis_weight is None else np.ascontiguousarray(axis_weight, dtype=np.float64)
+
+
+def solve_arrays(dim, n, kx, ky, kz, f, bc_type, bc_value, tol, length=(1.0, 1.0, 1.0), flvl=0.1,
+                 axis_weight=None, **opt) -> Result:
+    """Solve -div(K grad p) = f with the oracle's recursive multi-scale PCG.  axis_weight:
+    per-axis permeability scale for the aspect-ratio-aware level plan (None: uniform plan)."""
     L = lib()
+    aw = _axis_w(axis_weight)
     nx, ny, nz = n
     N = nx * ny * (nz if dim == 3 else 1)
     kx = _f64(kx)
@@ -144,7 +153,7 @@ def solve_arrays(dim, n, kx, ky, kz, f, bc_type, bc_value, tol, length=(1.0, 1.0
     Ld = np.asarray(length, dtype=np.float64)
     fl = np.array([flvl])
     L.oracle_solve(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), _d(f), bct, _d(bcv), float(tol), opt_p, _d(fl),
-                   _d(p), ctypes.byref(st))
+                   _d(p), ctypes.byref(st), _d(aw))
     nl = st.nlev
     return Result(p=p, status=st.status, outer_iters=st.outer_iters, nlev=nl,
                   level_n=[tuple(st.level_n[l]) for l in range(nl)],
@@ -159,11 +168,17 @@ def solve(problem, tol=None, **opt) -> Result:
                         problem.bc_value, problem.tol if tol is None else tol, length=problem.length, **opt)
 
 
-def level_plan(dim, n, scale=4, min_side=8, max_levels=MAX_LEVELS):
+def level_plan(dim, n, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None, length=(1.0, 1.0, 1.0)):
     L = lib()
     dims = (ctypes.c_int * (3 * MAX_LEVELS))()
     npt, _a = _i(n)
-    nl = L.oracle_level_plan(dim, npt, scale, min_side, max_levels, ctypes.cast(dims, ctypes.POINTER(ctypes.c_int)))
+    if axis_weight is None:
+        nl = L.oracle_level_plan(dim, npt, scale, min_side, max_levels, ctypes.cast(dims, ctypes.POINTER(ctypes.c_int)))
+    else:
+        Ld = np.asarray(length, dtype=np.float64)
+        aw = _axis_w(axis_weight)
+        nl = L.oracle_level_plan_semi(dim, npt, _d(Ld), _d(aw), scale, min_side, max_levels,
+                                      ctypes.cast(dims, ctypes.POINTER(ctypes.c_int)))
     return [tuple(dims[3 * l:3 * l + 3]) for l in range(nl)]
 
 
@@ -261,9 +276,10 @@ def cholesky_solve(Lf, b):
     return x
 
 
-def precond(problem, r, eps2=0.0, flvl=0.1, **opt):
+def precond(problem, r, eps2=0.0, flvl=0.1, axis_weight=None, **opt):
     """z = M_0^-1 r on the problem's hierarchy (level-0 preconditioner of eq. 2.10)."""
     L = lib()
+    aw = _axis_w(axis_weight)
     dim, n = problem.dim, problem.n
     kx = _f64(problem.kx)
     ky = _f64(problem.ky)
@@ -274,17 +290,18 @@ def precond(problem, r, eps2=0.0, flvl=0.1, **opt):
     z = np.zeros(problem.N)
     Ld = np.asarray(problem.length, dtype=np.float64)
     rc = L.oracle_precond(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), bct, o, float(flvl), float(eps2),
-                          _d(_f64(r)), _d(z))
+                          _d(_f64(r)), _d(z), _d(aw))
     if rc != 0:
         raise RuntimeError(f"oracle_precond failed: {rc}")
     return z
 
 
-def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS):
+def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None):
     """Per-level face arrays [(dims, tx, ty, tz), ...] of the problem's hierarchy."""
     L = lib()
     dim, n = problem.dim, problem.n
-    plan = level_plan(dim, n, scale, min_side, max_levels)
+    aw = _axis_w(axis_weight)
+    plan = level_plan(dim, n, scale, min_side, max_levels, axis_weight=aw, length=problem.length)
     sizes = []
     total = 0
     for d in plan:
@@ -299,7 +316,7 @@ def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS):
     Ld = np.asarray(problem.length, dtype=np.float64)
     kz = _f64(problem.kz) if dim == 3 else None
     nl = L.oracle_hierarchy_T(dim, npt, _d(Ld), _d(_f64(problem.kx)), _d(_f64(problem.ky)), _d(kz), bct, scale,
-                              min_side, max_levels, _d(out), out.size)
+                              min_side, max_levels, _d(out), out.size, _d(aw))
     assert nl == len(plan), (nl, plan)
     res = []
     off = 0

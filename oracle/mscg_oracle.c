@@ -96,6 +96,37 @@ int oracle_level_plan(int dim, const int n[3], int scale, int min_side, int max_
   return nl;
 }
 
+/* Aspect-ratio-aware plan (Section 5, anisotropic strip: coarsening aims at
+ * cells of aspect ratio 1, so the finer direction is coarsened first, then
+ * both).  The effective size of a cell along axis a is h_a / sqrt(w_a), with
+ * w_a the caller's permeability scale of that axis (e.g. kz / kx).  Per level,
+ * among the axes that can be coarsened by `scale` (exact division, coarse side
+ * >= min_side), those whose effective size is within a factor sqrt(scale) of
+ * the smallest are coarsened; the plan stops when no axis can be. */
+int oracle_level_plan_semi(int dim, const int n[3], const double Ldom[3], const double w[3], int scale, int min_side,
+                           int max_levels, int dims[][3]) {
+  int d[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+  int nl = 0;
+  if (max_levels > OR_MAX_LEVELS) max_levels = OR_MAX_LEVELS;
+  for (;;) {
+    dims[nl][0] = d[0]; dims[nl][1] = d[1]; dims[nl][2] = d[2];
+    nl++;
+    if (nl >= max_levels) break;
+    int can[3] = {0, 0, 0}, any = 0;
+    double e[3] = {0.0, 0.0, 0.0}, emin = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      can[a] = d[a] % scale == 0 && d[a] / scale >= min_side;
+      e[a] = (Ldom[a] / d[a]) / sqrt(w[a]);
+      if (can[a] && (!any || e[a] < emin)) emin = e[a];
+      any |= can[a];
+    }
+    if (!any) break;
+    for (int a = 0; a < dim; ++a)
+      if (can[a] && e[a] <= emin * sqrt((double)scale) * (1.0 + 1e-12)) d[a] /= scale;
+  }
+  return nl;
+}
+
 /* ------------------------------------------------------------------------ */
 /* a1: face transmissibilities (Section 3: harmonic mean of the two cells,   */
 /* T_xx = (dy/dx) K_xx, T_yy = (dx/dy) K_yy; boundary type changes the       */
@@ -499,11 +530,12 @@ static void free_problem(or_problem *P) {
  * factor on the coarsest level.  Returns 0, or -1 / -6 on error. */
 static int build_problem(or_problem *P, int dim, const int n[3], const double Ldom[3], const double *kx,
                          const double *ky, const double *kz, const int bc_type[6], int scale, int min_side,
-                         int max_levels, int max_coarse, int factor) {
+                         int max_levels, int max_coarse, int factor, const double *axis_w) {
   int dims[OR_MAX_LEVELS][3];
   memset(P, 0, sizeof(*P));
   P->dim = dim;
-  P->nlev = oracle_level_plan(dim, n, scale, min_side, max_levels, dims);
+  P->nlev = axis_w ? oracle_level_plan_semi(dim, n, Ldom, axis_w, scale, min_side, max_levels, dims)
+                   : oracle_level_plan(dim, n, scale, min_side, max_levels, dims);
   for (int l = 0; l < P->nlev; ++l) {
     or_level *L = &P->lev[l];
     L->nx = dims[l][0]; L->ny = dims[l][1]; L->nz = dims[l][2];
@@ -545,7 +577,7 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
  * non-positive entries take the defaults 4, 8, scale, 0.1, 200, 200, 8, 1024. */
 int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
                  const double *kz, const double *f, const int bc_type[6], const double bc_value[6], double tol,
-                 const int iopt[7], const double *flvl_opt, double *p_out, or_stats *st) {
+                 const int iopt[7], const double *flvl_opt, double *p_out, or_stats *st, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
   int m = iopt && iopt[2] > 0 ? iopt[2] : scale;
@@ -558,7 +590,7 @@ int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double 
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   memset(st, 0, sizeof(*st));
   or_problem P;
-  int rc = build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 1024, 1);
+  int rc = build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 1024, 1, axis_w);
   if (rc != 0) { free_problem(&P); st->status = rc; return rc; }
   P.m = m; P.flvl = flvl; P.max_outer = max_outer; P.max_inner = max_inner;
   or_level *L0 = &P.lev[0];
@@ -689,7 +721,7 @@ void oracle_restrict(int dim, const int fd[3], const int s[3], int interp, const
  * hierarchy has an exact coarse solve regardless). */
 int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
                    const double *kz, const int bc_type[6], const int iopt[7], double flvl, double eps2,
-                   const double *r, double *z) {
+                   const double *r, double *z, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
   int m = iopt && iopt[2] > 0 ? iopt[2] : scale;
@@ -699,7 +731,7 @@ int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const doubl
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   or_problem P;
-  int rc = build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 4096, 1);
+  int rc = build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 4096, 1, axis_w);
   if (rc != 0 || P.nlev < 2) { free_problem(&P); return rc != 0 ? rc : -1; }
   P.m = m; P.flvl = flvl > 0 ? flvl : 0.1; P.max_inner = max_inner; P.eps2 = eps2;
   precond(&P, 0, r, z);
@@ -711,11 +743,11 @@ int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const doubl
  * (tx, ty, tz per level).  Returns nlev, or a negative error. */
 int oracle_hierarchy_T(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
                        const double *kz, const int bc_type[6], int scale, int min_side, int max_levels,
-                       double *out, size_t out_len) {
+                       double *out, size_t out_len, const double *axis_w) {
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   or_problem P;
-  build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 0, 0);
+  build_problem(&P, dim, n, Ldom, kx, ky, kz, bc_type, scale, min_side, max_levels, 0, 0, axis_w);
   size_t off = 0;
   for (int l = 0; l < P.nlev; ++l) {
     or_level *L = &P.lev[l];

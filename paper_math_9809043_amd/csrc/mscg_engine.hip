@@ -86,6 +86,10 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   if (o->precision != MSCG_FP64 && o->precision != MSCG_MIXED) return fail(MSCG_E_ARG, "bad precision");
   if (o->max_outer_iters < 1 || o->max_inner_iters < 1) return fail(MSCG_E_ARG, "iteration caps must be >= 1");
   int maxl = o->max_levels < 1 ? 1 : (o->max_levels > MSCG_MAX_LEVELS ? MSCG_MAX_LEVELS : o->max_levels);
+  if (o->semi_coarsen != 0 && o->semi_coarsen != 1) return fail(MSCG_E_ARG, "semi_coarsen must be 0 or 1");
+  if (o->semi_coarsen)
+    for (int a = 0; a < g->dim; ++a)
+      if (!(o->axis_weight[a] > 0.0)) return fail(MSCG_E_ARG, "axis_weight[%d] must be > 0", a);
   int nl = 0;
   for (;;) {
     LevelPlan& L = P->lv[nl];
@@ -93,6 +97,23 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
     L.n = d[0] * d[1] * d[2];
     ++nl;
     if (nl >= maxl) break;
+    if (o->semi_coarsen) {
+      // aspect-ratio-aware: coarsen the axes whose effective cell size is within
+      // sqrt(scale) of the smallest among those that can be coarsened
+      bool can[3] = {false, false, false}, any = false;
+      double e[3] = {0.0, 0.0, 0.0}, emin = 0.0;
+      for (int a = 0; a < g->dim; ++a) {
+        const double len = g->length[a] > 0.0 ? g->length[a] : 1.0;
+        can[a] = d[a] % o->scale == 0 && d[a] / o->scale >= o->min_coarse_side;
+        e[a] = (len / d[a]) / std::sqrt(o->axis_weight[a]);
+        if (can[a] && (!any || e[a] < emin)) emin = e[a];
+        any = any || can[a];
+      }
+      if (!any) break;
+      for (int a = 0; a < g->dim; ++a)
+        if (can[a] && e[a] <= emin * std::sqrt((double)o->scale) * (1.0 + 1e-12)) d[a] /= o->scale;
+      continue;
+    }
     bool ok = true;
     for (int a = 0; a < g->dim; ++a)
       if (d[a] % o->scale != 0 || d[a] / o->scale < o->min_coarse_side) ok = false;
@@ -549,6 +570,8 @@ void mscg_default_options(mscg_options* o) {
   o->interp = MSCG_INTERP_LINEAR;
   o->flexible = 0;
   o->inner_rel_floor = 1e-6;
+  o->semi_coarsen = 0;
+  o->axis_weight[0] = o->axis_weight[1] = o->axis_weight[2] = 1.0;
 }
 
 const char* mscg_last_error(void) { return g_err.c_str(); }

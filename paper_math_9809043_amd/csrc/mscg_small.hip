@@ -103,7 +103,15 @@ __global__ void __launch_bounds__(kThreads, 1) k_small_reg(RegArgs a) {
     dg[u] = d;
     di[u] = R(1) / d;
     r[u] = c < n ? static_cast<const R*>(a.rhs)[cc] : R(0);
-    if (c < n) xv[c] = R(0);
+    // z and p are cleared too: at the domain boundary a cell's neighbour index
+    // falls back to the cell itself with a zero coefficient, and in the first
+    // half sweep that cell has not been written yet; LDS keeps whatever the
+    // previous kernel left there, and 0 times a NaN or Inf pattern is NaN
+    if (c < n) {
+      xv[c] = R(0);
+      z[c] = R(0);
+      pv[c] = R(0);
+    }
   }
   auto own = [&](int u) { return tid + u * kThreads < n; };
   auto colour = [&](int u) { return ((ijk[u] & 0xfff) + ((ijk[u] >> 12) & 0xfff) + (ijk[u] >> 24)) & 1; };
@@ -297,12 +305,8 @@ __global__ void __launch_bounds__(kThreads, 1) k_small_reg(RegArgs a) {
 
 template <typename R>
 hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
-  // 2-D levels go to the colour-split kernel (both precisions).  The FP32
-  // instantiation of the cell-strided kernel below gave results that changed
-  // from run to run on the GPU (identical inputs, occasional non-finite
-  // reductions) while its FP64 one is bitwise repeatable; until the cause is
-  // found, FP32 levels that the colour-split kernel does not take use the
-  // generic one-workgroup solver.
+  // 2-D levels go to the colour-split kernel (both precisions), the rest to
+  // the cell-strided kernel below.
   const int ks = d.ks, L = d.nlev - 1;
   if (ks + 1 != L) return hipErrorNotSupported;
   const Lv<R>& V = d.L[ks];
@@ -314,7 +318,6 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
     const hipError_t e = launch_small_2d<R>(d, s);
     if (e != hipErrorNotSupported) return e;
   }
-  if (sizeof(R) != sizeof(double)) return hipErrorNotSupported;
   RegArgs a{};
   a.dim = V.tz ? 3 : 2;
   a.nx = V.nx; a.ny = V.ny; a.nz = V.nz; a.n = V.n;

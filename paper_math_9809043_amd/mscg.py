@@ -39,7 +39,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("scale", ctypes.c_int), ("smooth_steps", ctypes.c_int),
                 ("level_factor", ctypes.c_double), ("min_coarse_side", ctypes.c_int), ("max_levels", ctypes.c_int),
                 ("max_outer_iters", ctypes.c_int), ("max_inner_iters", ctypes.c_int), ("interp", ctypes.c_int),
-                ("flexible", ctypes.c_int), ("inner_rel_floor", ctypes.c_double)]
+                ("flexible", ctypes.c_int), ("inner_rel_floor", ctypes.c_double), ("semi_coarsen", ctypes.c_int),
+                ("axis_weight", ctypes.c_double * 3)]
 
 
 class _Stats(ctypes.Structure):
@@ -162,11 +163,17 @@ class Options:
     interp: int = INTERP_LINEAR
     flexible: int = 0
     inner_rel_floor: float = 1e-6
+    semi_coarsen: int = 0
+    axis_weight: tuple = (1.0, 1.0, 1.0)
 
     def _c(self) -> _Options:
         o = _Options()
         for name, _ in _Options._fields_:
-            setattr(o, name, getattr(self, name))
+            if name == "axis_weight":
+                for a in range(3):
+                    o.axis_weight[a] = float(self.axis_weight[a])
+            else:
+                setattr(o, name, getattr(self, name))
         if o.smooth_steps <= 0:
             o.smooth_steps = o.scale
         return o

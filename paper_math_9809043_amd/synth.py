@@ -136,6 +136,22 @@ def layered_3d(seed: int, n: int = 128, ny: int | None = None, nz: int | None = 
                    bc_value=[bc_value[0], bc_value[1], 0.0, 0.0, 0.0, 0.0], tol=tol)
 
 
+def anisotropic_strip_2d(seed: int, nx: int = 512, ny: int = 128, ratio: float = 100.0, lo: float = -1.0,
+                         hi: float = 1.0, tol: float = 1e-10, name: str | None = None) -> Problem:
+    """A strip nx/ny times longer than wide (square cells) with ky = ratio * kx.
+
+    log10 kx ~ U[lo, hi] i.i.d., 3x3 box-smoothed; ky = ratio * kx; Dirichlet
+    p = 0 / 1 on the two short (x) ends, no flow on the long sides; f ~ N(0, 1).
+    The stand-in for the paper's flow in a narrow channel (Section 5).
+    """
+    rng = _rng(seed)
+    u = rng.uniform(lo, hi, size=(ny, nx))
+    f = rng.standard_normal(size=(ny, nx))
+    k = (10.0 ** _box3_mean(u)).reshape(-1)
+    return Problem(name=name or f"strip{nx}x{ny}_s{seed}", dim=2, n=(nx, ny, 1), kx=k, ky=k * ratio, kz=None,
+                   f=f.reshape(-1).copy(), length=(nx / ny, 1.0, 1.0), tol=tol)
+
+
 def small_case(seed: int = 0) -> Problem:
     """32x32, log10 k ~ U[-1, 1] box-smoothed, FP64, tolerance 1e-10."""
     return smoothed_lognormal_2d(seed, 32, lo=-1.0, hi=1.0, tol=1e-10, name=f"small32_s{seed}")

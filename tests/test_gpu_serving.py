@@ -139,3 +139,36 @@ def test_repeated_solves_are_bitwise_identical():
                     ref = x
                 else:
                     assert np.array_equal(ref, x), (prec, side, rep)
+
+
+def test_one_workgroup_solvers_ignore_what_lds_held_before():
+    """Solves of a 3-D semi-coarsened problem (last inner level in the cell-
+    strided one-workgroup kernel) give the same bits whatever ran before them:
+    other problems' kernels leave arbitrary data in LDS, which a boundary cell
+    must never read (it once did, through a zero coefficient times a stale
+    value, and 0 * NaN is NaN)."""
+    case("one-workgroup solvers after other kernels")
+    import torch
+    from paper_math_9809043_amd import mscg
+    cube = synth.layered_3d(2, 32, n_layers=4)
+    strip = synth.anisotropic_strip_2d(4, 512, 128)
+
+    def run(P, prec, **o):
+        grid = mscg.Grid(dim=P.dim, n=P.n, bc_type=P.bc_type, bc_value=P.bc_value, length=P.length)
+        prob = mscg.Problem(grid, mscg.Options(precision=prec, semi_coarsen=1, **o))
+        prob.set_permeability(torch.tensor(P.kx, device="cuda"), torch.tensor(P.ky, device="cuda"),
+                              torch.tensor(P.kz, device="cuda") if P.dim == 3 else None)
+        p = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        st = prob.solve(torch.tensor(P.f, device="cuda"), p, P.tol)
+        torch.cuda.synchronize()
+        return st, p.cpu().numpy()
+
+    for prec in (mscg.FP64, mscg.MIXED):
+        ref = None
+        for rep in range(3):
+            run(strip, prec, axis_weight=(1, 100, 1))
+            st, x = run(cube, prec, axis_weight=(1, 1, 0.01), interp=1)
+            assert st.status == 0 and st.rel_residual_true <= 1e-10, (prec, rep, mscg.last_error())
+            if ref is None:
+                ref = x
+            assert np.array_equal(ref, x), (prec, rep)

@@ -486,3 +486,76 @@ def test_all_neumann_is_singular():
     P.bc_type = [0, 0, 0, 0, 0, 0]
     r = oracle.solve(P)
     assert r.status == -6
+
+
+# ------------------------------------------------------- semi-coarsening (Section 5)
+
+@pytest.mark.parametrize("dim,n,length", [(2, (1024, 1024, 1), (1, 1, 1)), (2, (32, 32, 1), (1, 1, 1)),
+                                          (2, (288, 160, 1), (1, 1, 1)), (3, (128, 128, 128), (1, 1, 1)),
+                                          (3, (32, 32, 32), (1, 1, 1))])
+def test_semi_plan_with_equal_weights_is_the_uniform_plan(dim, n, length):
+    """With no anisotropy and near-square cells every axis is coarsened together."""
+    assert oracle.level_plan(dim, n, axis_weight=(1, 1, 1), length=length) == oracle.level_plan(dim, n)
+
+
+def effective_sizes(dims, length, w):
+    return [length[a] / dims[a] / np.sqrt(w[a]) for a in range(len(w))]
+
+
+@pytest.mark.parametrize("dim,n,length,w", [(2, (512, 128, 1), (4, 1, 1), (1, 100, 1)),
+                                            (2, (2048, 512, 1), (4, 1, 1), (1, 100, 1)),
+                                            (3, (128, 128, 128), (1, 1, 1), (1, 1, 0.01)),
+                                            (3, (32, 32, 32), (1, 1, 1), (1, 1, 0.01))])
+def test_semi_plan_coarsens_the_finest_direction_first(dim, n, length, w):
+    """Section 5: coarsening aims at cells of aspect ratio one, so the direction
+    in which cells are effectively smallest (the strongly coupled one) is
+    coarsened first.  At every level, an axis left alone while it could have
+    been coarsened is effectively coarser than every axis that was coarsened;
+    while no axis has reached its minimum side, the effective aspect ratio never
+    grows beyond its start or the factor 4."""
+    plan = oracle.level_plan(dim, n, axis_weight=w, length=length)
+    assert len(plan) >= 3
+    start = effective_sizes(plan[0], length, w[:dim])
+    first = [a for a in range(dim) if plan[1][a] != plan[0][a]]
+    assert first == [int(np.argmin(start[:dim]))] or (dim == 3 and first == [0, 1])
+    for cur, nxt in zip(plan, plan[1:]):
+        e = effective_sizes(cur, length, w[:dim])
+        done = [a for a in range(dim) if nxt[a] != cur[a]]
+        assert all(cur[a] == 4 * nxt[a] for a in done) and done
+        left = [a for a in range(dim) if a not in done and cur[a] % 4 == 0 and cur[a] // 4 >= 8]
+        for a in left:
+            assert all(e[a] > e[b] for b in done)
+        if all(cur[a] % 4 == 0 and cur[a] // 4 >= 8 for a in range(dim)):  # no axis at its limit yet
+            en = effective_sizes(nxt, length, w[:dim])
+            assert max(en) / min(en) <= max(max(start) / min(start), 4.0) + 1e-12
+
+
+def test_semi_coarsened_solve_matches_dense_solution():
+    """A 4:1 strip with ky = 100 kx, four semi-coarsened levels, against the
+    dense solution."""
+    P = synth.anisotropic_strip_2d(2, 64, 16)
+    h = (P.length[0] / 64, 1 / 16, 1)
+    tx, ty, _ = oracle.face_T(2, P.n, h, P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, P.n, tx, ty)
+    b = rhs(P, tx, ty)
+    x = np.linalg.solve(A, b)
+    for interp in (oracle.LINEAR, oracle.CONSTANT):
+        r = oracle.solve(P, tol=1e-10, min_side=2, interp=interp, axis_weight=(1, 100, 1))
+        assert r.status == 0 and r.nlev == 4
+        assert r.level_n == [(64, 16, 1), (64, 4, 1), (16, 4, 1), (4, 4, 1)]
+        assert np.linalg.norm(r.p - x) / np.linalg.norm(x) < 1e-8
+
+
+def test_semi_coarsening_helps_anisotropic_problems():
+    """The paper's observation on the anisotropic strip: aspect-ratio-aware
+    coarsening keeps the outer iteration count small where uniform coarsening
+    does not (here 7 against 61 on the strip, 5 against 200+ on the layered
+    cube with linear extension)."""
+    strip = synth.anisotropic_strip_2d(1, 512, 128)
+    uni = oracle.solve(strip)
+    semi = oracle.solve(strip, axis_weight=(1, 100, 1))
+    assert semi.status == 0 and semi.rel_residual_true < 1e-10
+    assert semi.outer_iters * 4 < uni.outer_iters
+    cube = synth.layered_3d(2, 32, n_layers=4)
+    semi3 = oracle.solve(cube, axis_weight=(1, 1, 0.01))
+    assert semi3.status == 0 and semi3.outer_iters <= 8
