@@ -242,6 +242,18 @@ def main():
             print(f"[bench] {key}: fp64 {wall3:.1f} ms (outer {st3.outer_iters}, levels {st3.level_iters}), "
                   f"mixed {wall3m:.1f} ms (outer {st3m.outer_iters})", flush=True)
 
+    if not args.no_3d and args.workload == "smooth1024":
+        # ablation: the modified Jacobi splitting (P = 2D) on the same problem
+        optj = dict(W["opt"])
+        optj["splitting"] = mscg.SPLIT_JACOBI
+        _, stj, wallj, solvej, _ = run_gpu(P, optj, 2, 1)
+        extra["smooth1024_jacobi"] = {"workload": W["desc"] + "; modified Jacobi splitting P = 2D on every level "
+                                      "(host-driven inner levels)", "fp64": {"value": round(P.N / (wallj * 1e-3), 1),
+                                      "ms_per_step": round(wallj, 3), "outer_iters": stj.outer_iters,
+                                      "level_iters": stj.level_iters, "rel_residual_true": stj.rel_residual_true}}
+        print(f"[bench] smooth1024 modified Jacobi: fp64 {wallj:.1f} ms (outer {stj.outer_iters}, levels "
+              f"{stj.level_iters})", flush=True)
+
     value = P.N / (wall_ms * 1e-3)
     line = {
         "metric": "unknowns solved/s to 1e-10 resid (set-up + solve), FP64 plain method; mixed alongside",

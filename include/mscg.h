@@ -62,6 +62,10 @@ enum { MSCG_FP64 = 0, MSCG_MIXED = 1 };
  * with zero slope at the boundary, or piecewise-constant interpolation (the
  * alternative the paper reports to work nearly as well). R = E^T. */
 enum { MSCG_INTERP_LINEAR = 0, MSCG_INTERP_CONSTANT = 1 };
+/* Splittings (Section 3): symmetric Gauss-Seidel in red-black order,
+ * P = (D+L) D^-1 (D+U); or modified Jacobi, P = 2D, fully parallel (every
+ * inner level then runs host-driven with grid-wide kernels). */
+enum { MSCG_SPLIT_SGS = 0, MSCG_SPLIT_JACOBI = 1 };
 
 typedef struct {
   int dim;            /* 2 or 3 */
@@ -89,6 +93,8 @@ typedef struct {
                              coarsened by `scale`, those whose effective cell size h_a / sqrt(axis_weight[a])
                              is within sqrt(scale) of the smallest are coarsened */
   double axis_weight[3];  /* permeability scale per axis for that plan (e.g. 1, 1, kz/kx), default 1 */
+  int splitting;          /* operator splitting A = P - Q of the smoother (eq. 2.3, Section 3):
+                             MSCG_SPLIT_SGS (default) or MSCG_SPLIT_JACOBI */
 } mscg_options;
 
 typedef struct {

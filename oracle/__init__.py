@@ -72,6 +72,8 @@ def lib():
         L.oracle_sgs.restype = None
         L.oracle_gs_colour.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, dp, dp, ctypes.c_int]
         L.oracle_gs_colour.restype = None
+        L.oracle_mjac.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, dp, dp, ctypes.c_int]
+        L.oracle_mjac.restype = None
         L.oracle_prolong_add.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
         L.oracle_prolong_add.restype = None
         L.oracle_restrict.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
@@ -123,8 +125,13 @@ LINEAR = 0
 CONSTANT = 1
 
 
-def _opts(scale=4, min_side=8, m=0, max_outer=200, max_inner=200, max_levels=MAX_LEVELS, interp=LINEAR):
-    return [scale, min_side, m, max_outer, max_inner, max_levels, interp]
+SGS = 0
+JACOBI = 1
+
+
+def _opts(scale=4, min_side=8, m=0, max_outer=200, max_inner=200, max_levels=MAX_LEVELS, interp=LINEAR,
+          splitting=SGS):
+    return [scale, min_side, m, max_outer, max_inner, max_levels, interp, splitting]
 
 
 def _axis_w(axis_weight):
@@ -227,6 +234,15 @@ def sgs(dim, n, T, r, x, m):
     tx, ty, tz = (_f64(T[0]), _f64(T[1]), _f64(T[2]) if T[2] is not None else None)
     x = np.array(x, dtype=np.float64, copy=True)
     L.oracle_sgs(dim, n[0], n[1], n[2] if dim == 3 else 1, _d(tx), _d(ty), _d(tz), _d(_f64(r)), _d(x), int(m))
+    return x
+
+
+def mjac(dim, n, T, r, x, m):
+    """m modified Jacobi steps (P = 2D); returns the new x."""
+    L = lib()
+    tx, ty, tz = (_f64(T[0]), _f64(T[1]), _f64(T[2]) if T[2] is not None else None)
+    x = np.array(x, dtype=np.float64, copy=True)
+    L.oracle_mjac(dim, n[0], n[1], n[2] if dim == 3 else 1, _d(tx), _d(ty), _d(tz), _d(_f64(r)), _d(x), int(m))
     return x
 
 

@@ -322,6 +322,31 @@ static void sgs_steps(const or_level *L, const double *r, double *x, int m) {
   }
 }
 
+/* The modified Jacobi splitting (Section 3): P = 2D, Q = D - U - L.  One step
+ * is x <- x + P^-1 (r - A x) = x + (r - A x) / (2 d) for every cell at once. */
+static void mjac_steps(const or_level *L, const double *r, double *x, int m) {
+  const size_t n = (size_t)L->nx * L->ny * L->nz;
+  double *ax = malloc(sizeof(double) * n);
+  for (int step = 0; step < m; ++step) {
+    apply_A(L, x, ax);
+    for (int k = 0; k < L->nz; ++k)
+      for (int j = 0; j < L->ny; ++j)
+        for (int i = 0; i < L->nx; ++i) {
+          size_t c = i + (size_t)L->nx * (j + (size_t)L->ny * k);
+          ax[c] = x[c] + (r[c] - ax[c]) / (2.0 * cell_diag(L, i, j, k));
+        }
+    memcpy(x, ax, sizeof(double) * n);
+  }
+  free(ax);
+}
+
+/* m steps of the chosen splitting: 0 symmetric Gauss-Seidel, 1 modified Jacobi */
+static int g_split = 0;
+static void smooth(const or_level *L, const double *r, double *x, int m) {
+  if (g_split == 1) mjac_steps(L, r, x, m);
+  else sgs_steps(L, r, x, m);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid transfers (Section 3): E = tensor product of 1-D linear              */
 /* interpolation between cell centres with zero slope at the boundary;       */
@@ -453,7 +478,7 @@ static int pcg_level(or_problem *P, int k, const double *b, double *x, int x_is_
 static void precond(or_problem *P, int k, const double *r, double *z) {
   or_level *L = &P->lev[k], *C = &P->lev[k + 1];
   memset(z, 0, sizeof(double) * L->n);
-  sgs_steps(L, r, z, P->m);
+  smooth(L, r, z, P->m);
   apply_A(L, z, L->s);
   for (int i = 0; i < L->n; ++i) L->s[i] = r[i] - L->s[i];
   restrict_T(L, C, L->s, C->t); /* coarse right-hand side */
@@ -465,7 +490,7 @@ static void precond(or_problem *P, int k, const double *r, double *z) {
     pcg_level(P, k + 1, C->t, C->x, 1, P->max_inner);
   }
   prolong_add(L, C, C->x, z);
-  sgs_steps(L, r, z, P->m);
+  smooth(L, r, z, P->m);
 }
 
 /* Conjugate gradient with preconditioner as in the Templates book, Section
@@ -573,11 +598,14 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
  * matrix is SPD).  Inputs on the host: cell-centred kx, ky, kz (kz only in
  * 3-D), source f; per-face BC type and value.  rhs b_c = f_c |V_c| plus, on
  * each Dirichlet boundary face, T_b p_D.  Output p (n cells).
- * opt: scale, min_side, m, flvl, max_outer, max_inner, max_levels, max_coarse;
- * non-positive entries take the defaults 4, 8, scale, 0.1, 200, 200, 8, 1024. */
+ * iopt: scale, min_side, m, max_outer, max_inner, max_levels, interp (0 linear,
+ * 1 piecewise constant), splitting (0 symmetric Gauss-Seidel, 1 modified Jacobi);
+ * non-positive entries take the defaults 4, 8, scale, 200, 200, 8, 0, 0.
+ * flvl_opt: f (default 0.1).  axis_w: NULL for the uniform level plan, else
+ * the per-axis weights of the aspect-ratio-aware plan. */
 int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
                  const double *kz, const double *f, const int bc_type[6], const double bc_value[6], double tol,
-                 const int iopt[7], const double *flvl_opt, double *p_out, or_stats *st, const double *axis_w) {
+                 const int iopt[8], const double *flvl_opt, double *p_out, or_stats *st, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
   int m = iopt && iopt[2] > 0 ? iopt[2] : scale;
@@ -585,6 +613,7 @@ int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double 
   int max_inner = iopt && iopt[4] > 0 ? iopt[4] : 200;
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
+  g_split = iopt && iopt[7] == 1 ? 1 : 0;
   double flvl = flvl_opt && *flvl_opt > 0.0 ? *flvl_opt : 0.1;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
@@ -688,6 +717,13 @@ void oracle_sgs(int dim, int nx, int ny, int nz, const double *tx, const double 
   sgs_steps(&L, r, x, m);
 }
 
+/* m modified Jacobi steps (P = 2D) from x, in place */
+void oracle_mjac(int dim, int nx, int ny, int nz, const double *tx, const double *ty, const double *tz,
+                 const double *r, double *x, int m) {
+  or_level L = make_view(dim, nx, ny, nz, tx, ty, tz);
+  mjac_steps(&L, r, x, m);
+}
+
 /* one Gauss-Seidel half sweep over one colour (0 red, 1 black), in place */
 void oracle_gs_colour(int dim, int nx, int ny, int nz, const double *tx, const double *ty, const double *tz,
                       const double *r, double *x, int colour) {
@@ -720,7 +756,7 @@ void oracle_restrict(int dim, const int fd[3], const int s[3], int interp, const
  * max_inner large runs the inner PCGs to their iteration cap; a 2-level
  * hierarchy has an exact coarse solve regardless). */
 int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
-                   const double *kz, const int bc_type[6], const int iopt[7], double flvl, double eps2,
+                   const double *kz, const int bc_type[6], const int iopt[8], double flvl, double eps2,
                    const double *r, double *z, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
@@ -728,6 +764,7 @@ int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const doubl
   int max_inner = iopt && iopt[4] > 0 ? iopt[4] : 200;
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
+  g_split = iopt && iopt[7] == 1 ? 1 : 0;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   or_problem P;

@@ -87,6 +87,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   if (o->max_outer_iters < 1 || o->max_inner_iters < 1) return fail(MSCG_E_ARG, "iteration caps must be >= 1");
   int maxl = o->max_levels < 1 ? 1 : (o->max_levels > MSCG_MAX_LEVELS ? MSCG_MAX_LEVELS : o->max_levels);
   if (o->semi_coarsen != 0 && o->semi_coarsen != 1) return fail(MSCG_E_ARG, "semi_coarsen must be 0 or 1");
+  if (o->splitting != MSCG_SPLIT_SGS && o->splitting != MSCG_SPLIT_JACOBI) return fail(MSCG_E_ARG, "bad splitting");
   if (o->semi_coarsen)
     for (int a = 0; a < g->dim; ++a)
       if (!(o->axis_weight[a] > 0.0)) return fail(MSCG_E_ARG, "axis_weight[%d] must be > 0", a);
@@ -339,6 +340,25 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
     if (e != hipSuccess && *rc == MSCG_OK) *rc = fail(MSCG_E_DEVICE, "precond level %d: %s", k, hipGetErrorString(e));
     return e == hipSuccess;
   };
+  if (P->o.splitting == MSCG_SPLIT_JACOBI) {
+    // m modified Jacobi steps from zero, alternating between z and w; the
+    // restriction's residual goes to the buffer not holding the iterate
+    R* cur = z;
+    R* nxt = w;
+    for (int step = 0; step < m; ++step) {
+      if (!chk(launch_mjac_step<R>(L, r, cur, nxt, step == 0, P->stream, gate))) return nullptr;
+      std::swap(cur, nxt);
+    }
+    if (!chk(launch_residual_restrict<R>(L, X, r, cur, nxt, rs[k + 1], P->stream, gate))) return nullptr;
+    *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs, gate);
+    if (*rc) return nullptr;
+    if (!chk(launch_prolong<R>(L, X, xs[k + 1], cur, P->stream, gate))) return nullptr;
+    for (int step = 0; step < m; ++step) {
+      if (!chk(launch_mjac_step<R>(L, r, cur, nxt, 0, P->stream, gate))) return nullptr;
+      std::swap(cur, nxt);
+    }
+    return cur;
+  }
   const bool tiled = P->tiled && smooth_tile_supported(L.nz, L.tz != nullptr, m);
   if (tiled) {
     if (!chk(launch_smooth_tile<R>(L, nullptr, r, nullptr, nullptr, z, m, P->tile_shape, P->stream, gate)))
@@ -572,6 +592,7 @@ void mscg_default_options(mscg_options* o) {
   o->inner_rel_floor = 1e-6;
   o->semi_coarsen = 0;
   o->axis_weight[0] = o->axis_weight[1] = o->axis_weight[2] = 1.0;
+  o->splitting = MSCG_SPLIT_SGS;
 }
 
 const char* mscg_last_error(void) { return g_err.c_str(); }
@@ -634,8 +655,9 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   if (rc) { mscg_destroy_problem(P); return rc; }
   const int sn = small_n();
   P->ks = P->nlev;  // no small level
-  for (int l = 1; l < P->nlev - 1; ++l)
-    if (P->lev[l].n <= sn) { P->ks = l; break; }
+  if (P->o.splitting == MSCG_SPLIT_SGS)  // the one-workgroup solvers smooth by red-black SGS only
+    for (int l = 1; l < P->nlev - 1; ++l)
+      if (P->lev[l].n <= sn) { P->ks = l; break; }
   for (int l = 0; l < P->nlev; ++l) {
     LevelH& L = P->lev[l];
     L.hx = P->g.length[0] / L.nx;

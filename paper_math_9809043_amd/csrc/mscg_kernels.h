@@ -100,6 +100,11 @@ hipError_t launch_cg_update(R* x, R* r, const R* p, const R* q, int n, const Sca
 template <typename R>
 hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int first, hipStream_t s,
                           const int* gate = nullptr);
+// One modified Jacobi step xout = xin + (r - A xin) / (2d) (xin = 0 when first);
+// xout must not alias xin.
+template <typename R>
+hipError_t launch_mjac_step(const Lv<R>& L, const R* r, const R* xin, R* xout, int first, hipStream_t s,
+                            const int* gate = nullptr);
 template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s);
 template <typename R>

@@ -465,6 +465,27 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(R* __restrict__ x, R* __re
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// One step of the modified Jacobi splitting (P = 2D, Q = D - U - L, Section 3):
+// xout = xin + (r - A xin) / (2 d) for every cell; first: xin = 0, so
+// xout = r / (2 d).  xout must not alias xin.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_mjac_step(Lv<R> L, const R* __restrict__ r, const R* __restrict__ xin,
+                                                       R* __restrict__ xout, int first, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, L.nx, L.ny, i, j, k);
+    R d, o;
+    if (first) {
+      stencil_at(L, r, i, j, k, c, d, o);  // only d is used
+      xout[c] = (r[c] - R(0)) / (R(2) * d);
+    } else {
+      stencil_at(L, xin, i, j, k, c, d, o);
+      xout[c] = xin[c] + (r[c] - (d * xin[c] - o)) / (R(2) * d);
+    }
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gs_half(Lv<R> L, const R* __restrict__ r, R* __restrict__ x, int colour,
                                                      int first, const int* __restrict__ gate) {
@@ -993,6 +1014,13 @@ hipError_t launch_gs_half(const Lv<R>& L, const R* r, R* x, int colour, int firs
 }
 
 template <typename R>
+hipError_t launch_mjac_step(const Lv<R>& L, const R* r, const R* xin, R* xout, int first, hipStream_t s,
+                            const int* gate) {
+  hipLaunchKernelGGL(k_mjac_step<R>, dim3(grid_for(L.n, 1 << 20)), dim3(kBlock), 0, s, L, r, xin, xout, first, gate);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s) {
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
   hipLaunchKernelGGL(k_restrict<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X, r, x, g);
@@ -1152,6 +1180,7 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
   template hipError_t launch_update_p<R>(const R*, R*, int, const Scal*, hipStream_t);                            \
   template hipError_t launch_cg_update<R>(R*, R*, const R*, const R*, int, const Scal*, double*, int, hipStream_t); \
   template hipError_t launch_gs_half<R>(const Lv<R>&, const R*, R*, int, int, hipStream_t, const int*);          \
+  template hipError_t launch_mjac_step<R>(const Lv<R>&, const R*, const R*, R*, int, hipStream_t, const int*);    \
   template hipError_t launch_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, hipStream_t);         \
   template hipError_t launch_residual_restrict<R>(const Lv<R>&, const Xfer&, const R*, const R*, R*, R*, hipStream_t, \
                                                   const int*);                                                     \

@@ -329,3 +329,33 @@ def test_semi_coarsening_parity(name, make, w, opt):
     assert st.rel_residual_true <= max(tol, 1e-10)
     assert err <= 1e-8
     assert abs(st.outer_iters - ref.outer_iters) <= 2
+
+
+JACOBI_CASES = [
+    ("small32", lambda: synth.small_case(3), {}),
+    ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
+    ("rect288x160_const", lambda: synth.smoothed_lognormal_2d(7, 288, 160, lo=-2, hi=2), {"interp": 1}),
+    ("layered32_semi", lambda: synth.layered_3d(3, 32, n_layers=8), {"interp": 1, "semi": (1, 1, 0.01)}),
+]
+
+
+@pytest.mark.parametrize("name,make,opt", JACOBI_CASES, ids=[c[0] for c in JACOBI_CASES])
+def test_modified_jacobi_parity(name, make, opt):
+    """Modified Jacobi splitting (P = 2D, Section 3) on every level, against the oracle."""
+    case(f"modified Jacobi solve {name}")
+    from paper_math_9809043_amd import mscg
+    P = make()
+    opt = dict(opt)
+    semi = opt.pop("semi", None)
+    gopt = dict(opt, splitting=mscg.SPLIT_JACOBI)
+    if semi:
+        gopt.update(semi_coarsen=1, axis_weight=semi)
+    st, x, _ = gpu_solve(P, **gopt)
+    ref = oracle.solve(P, splitting=oracle.JACOBI, axis_weight=semi, **oracle_opts(opt))
+    err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+    print(f"  gpu outer={st.outer_iters} levels={st.level_iters} | oracle outer={ref.outer_iters} "
+          f"levels={ref.level_iters} | rel err {err:.2e}", flush=True)
+    assert ref.status == 0 and st.status == 0
+    assert st.rel_residual_true <= 1e-10
+    assert err <= 1e-8
+    assert abs(st.outer_iters - ref.outer_iters) <= 2

@@ -385,6 +385,31 @@ def test_sgs_splitting():
 
 # ---------------------------------------------------------------- preconditioner (eqs. 2.5, 2.7a, 2.10)
 
+def test_modified_jacobi_splitting():
+    """P = 2D, Q = D - U - L (Section 3): a step applies x + (2D)^-1 (r - A x),
+    P - Q = A, and unlike plain Jacobi the iteration damps the checkerboard
+    mode (the spectrum of P^-1 Q stays inside (-1, 1))."""
+    n = (8, 6, 1)
+    P = problem_2d(n[:2], lo=-2, hi=2, seed=4)
+    tx, ty, _ = oracle.face_T(2, n, (1 / 8, 1 / 6, 1), P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, n, tx, ty)
+    D = np.diag(np.diag(A))
+    Pm, Qm = 2 * D, D - (A - D)
+    assert np.allclose(Pm - Qm, A)
+    T = (tx, ty, None)
+    x = RNG.standard_normal(48)
+    r = RNG.standard_normal(48)
+    assert np.allclose(oracle.mjac(2, n, T, r, x, 1), x + np.linalg.solve(Pm, r - A @ x), atol=1e-12)
+    x3 = x.copy()
+    for _ in range(3):
+        x3 = x3 + np.linalg.solve(Pm, r - A @ x3)
+    assert np.allclose(oracle.mjac(2, n, T, r, x, 3), x3, atol=1e-12)
+    ev = np.linalg.eigvals(np.linalg.solve(Pm, Qm)).real
+    assert ev.max() < 1 and ev.min() > -1
+    ev_plain = np.linalg.eigvals(np.linalg.solve(D, D - A)).real
+    assert ev_plain.min() < ev.min()  # plain Jacobi leaves the checkerboard mode near -1
+
+
 def two_level_dense(P, interp, m=4):
     n = P.n
     h = (1 / n[0], 1 / n[1], 1)
@@ -416,18 +441,23 @@ def two_level_dense(P, interp, m=4):
     return A, Ac, E, Pm, Qm
 
 
-@pytest.mark.parametrize("interp", [oracle.LINEAR, oracle.CONSTANT])
-def test_preconditioner_is_eq_2_10(interp):
+@pytest.mark.parametrize("interp,splitting", [(oracle.LINEAR, oracle.SGS), (oracle.CONSTANT, oracle.SGS),
+                                              (oracle.LINEAR, oracle.JACOBI)])
+def test_preconditioner_is_eq_2_10(interp, splitting):
     P = problem_2d((16, 16), lo=-3, hi=3, seed=7)
     m = 4
     A, Ac, E, Pm, Qm = two_level_dense(P, interp, m)
+    if splitting == oracle.JACOBI:
+        D = np.diag(np.diag(A))
+        Pm, Qm = 2 * D, D - (A - D)
     N = A.shape[0]
     Pinv = np.linalg.inv(Pm)
     H = Pinv @ Qm
     W = E @ np.linalg.solve(Ac, E.T)
     Hm = np.linalg.matrix_power(H, m)
     Minv = Hm @ W @ Hm.T + sum(np.linalg.matrix_power(H, j) @ Pinv for j in range(2 * m))
-    got = np.stack([oracle.precond(P, e, interp=interp, max_levels=2, min_side=2) for e in np.eye(N)], axis=1)
+    got = np.stack([oracle.precond(P, e, interp=interp, max_levels=2, min_side=2, splitting=splitting)
+                    for e in np.eye(N)], axis=1)
     assert np.allclose(got, Minv, rtol=0, atol=1e-10 * np.abs(Minv).max())
     # symmetric positive definite (Tatebe's condition, Section 2)
     assert np.allclose(got, got.T, atol=1e-12 * np.abs(got).max())
@@ -489,6 +519,19 @@ def test_all_neumann_is_singular():
 
 
 # ------------------------------------------------------- semi-coarsening (Section 5)
+
+@pytest.mark.parametrize("n", [(32, 32), (64, 32)])
+def test_jacobi_solve_matches_dense_solution(n):
+    P = problem_2d(n, lo=-2, hi=2, seed=5)
+    h = (1 / n[0], 1 / n[1], 1)
+    tx, ty, _ = oracle.face_T(2, P.n, h, P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, P.n, tx, ty)
+    b = rhs(P, tx, ty)
+    x = np.linalg.solve(A, b)
+    r = oracle.solve(P, tol=1e-10, splitting=oracle.JACOBI, min_side=2)
+    assert r.status == 0 and r.nlev >= 3
+    assert np.linalg.norm(r.p - x) / np.linalg.norm(x) < 1e-8
+
 
 @pytest.mark.parametrize("dim,n,length", [(2, (1024, 1024, 1), (1, 1, 1)), (2, (32, 32, 1), (1, 1, 1)),
                                           (2, (288, 160, 1), (1, 1, 1)), (3, (128, 128, 128), (1, 1, 1)),
