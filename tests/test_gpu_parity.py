@@ -359,3 +359,44 @@ def test_modified_jacobi_parity(name, make, opt):
     assert st.rel_residual_true <= 1e-10
     assert err <= 1e-8
     assert abs(st.outer_iters - ref.outer_iters) <= 2
+
+
+def test_one_row_grids():
+    """Degenerate 2-D grids one cell tall: with every axis coarsened together
+    they cannot coarsen (a single, directly solved level, or an error when it
+    exceeds the dense limit); the aspect-ratio-aware plan coarsens x alone."""
+    from paper_math_9809043_amd import mscg
+    case("one-row grids")
+    P = synth.smoothed_lognormal_2d(3, 64, 1, lo=-2, hi=2)
+    st, x, prob = gpu_solve(P)
+    ref = oracle.solve(P)
+    assert prob.n_levels == 1 and st.status == 0
+    assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) <= 1e-8
+    Q = synth.smoothed_lognormal_2d(3, 4096, 1, lo=-2, hi=2)
+    with pytest.raises(mscg.MscgError):
+        make_problem(Q)
+    st, x, prob = gpu_solve(Q, semi_coarsen=1)
+    ref = oracle.solve(Q, axis_weight=(1, 1, 1))
+    assert [tuple(d) for d in st.level_n] == [tuple(d) for d in ref.level_n] and prob.n_levels == 5
+    assert st.status == 0 and st.rel_residual_true <= 1e-10
+    assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) <= 1e-8
+    assert abs(st.outer_iters - ref.outer_iters) <= 2
+
+
+def test_full_size_1024_matches_oracle():
+    """The bench's workload at full size (1024^2, contrast 1e6, tol 1e-10) in
+    the bench's launch configuration, FP64 and mixed, against the oracle's full
+    solution."""
+    from paper_math_9809043_amd import mscg
+    case("full-size smooth1024")
+    P = synth.smoothed_lognormal_2d(0, 1024, lo=-3.0, hi=3.0, tol=1e-10, name="smooth1024")
+    ref = oracle.solve(P)
+    assert ref.status == 0
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: outer {st.outer_iters} (oracle {ref.outer_iters}) levels {st.level_iters} "
+              f"(oracle {ref.level_iters}) res {st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
