@@ -102,7 +102,7 @@ __device__ __forceinline__ A spmv_range(const Lv<R>& L, const R* __restrict__ x,
 }
 
 // One red-black Gauss-Seidel half sweep: every cell of `colour` ((i+j+k) mod 2,
-// red = 0) gets x_c = (r_c + sum T_f x_nb) / diag (Section 3, symmetric
+// red = 0) gets x_c = (r_c + sum T_f x_nb) * (1 / diag) (Section 3, symmetric
 // Gauss-Seidel splitting in red-black order).  `first`: the sweep starts from
 // x = 0, so the neighbours are not read.
 template <typename R>
@@ -132,7 +132,7 @@ __device__ __forceinline__ void gs_half_range(const Lv<R>& L, const R* __restric
     } else {
       stencil_at(L, x, i, j, k, c, d, o);
     }
-    x[c] = (r[c] + o) / d;
+    x[c] = (r[c] + o) * (R(1) / d);  // the tiled smoother forms the same inverse once per cell
   }
 }
 

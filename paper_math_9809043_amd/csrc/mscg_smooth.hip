@@ -10,11 +10,11 @@
 //
 // Layout: thread (k, row group) owns the k-th red and the k-th black cell of
 // each of its rows and keeps their four neighbour coefficients (zero across
-// the domain or region edge), diagonal and r in registers, all loaded in one
+// the domain or region edge), inverse diagonal and r in registers, all loaded in one
 // batch.  z lives in LDS split by colour, so the cells a half sweep updates
 // are contiguous and their neighbours are contiguous in the other colour's
-// array.  The update is z = (r + sum T z_nb) / d with the terms in the same
-// order as the grid-wide half sweep, so both give the same bits.  The
+// array.  The update is z = (r + sum T z_nb) * (1 / d) with the terms in the
+// same order as the grid-wide half sweep, so both give the same bits.  The
 // post-smoothing variant also applies the prolongation z = z_pre + E y while
 // loading.
 #include <hip/hip_runtime.h>
@@ -65,13 +65,13 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
       const int q = (rx0 + ry0 + lj + c) & 1;
       const int li = 2 * k + q;
       cw[b][c] = ce[b][c] = cs[b][c] = cn[b][c] = R(0);
-      dg[b][c] = R(1);
+      dg[b][c] = R(1);  // inverse diagonal
       rr[b][c] = R(0);
       if (lj < RH && li < RW) {
         const int i = rx0 + li;
         const int fx = i + (nx + 1) * j, fy = i + nx * j;
         const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
-        dg[b][c] = tw + te + ts + tn;
+        dg[b][c] = R(1) / (tw + te + ts + tn);
         if (i > 0 && li > 0) cw[b][c] = tw;
         if (i < nx - 1 && li < RW - 1) ce[b][c] = te;
         if (j > 0 && lj > 0) cs[b][c] = ts;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
           if (cs[b][c] != R(0)) o += cs[b][c] * zc[oc][s][k];
           if (cn[b][c] != R(0)) o += cn[b][c] * zc[oc][n][k];
         }
-        zc[c][lj][k] = (rr[b][c] + o) / dg[b][c];
+        zc[c][lj][k] = (rr[b][c] + o) * dg[b][c];
       }
     }
     __syncthreads();
