@@ -48,10 +48,35 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
   // li = 2k + ((rx0 + ry0 + lj + c) & 1).
   int xI0[2], xI1[2];
   R xw0[2], xw1[2];
+  // post-smoothing: the coarse values the region's prolongation reads are
+  // staged in LDS when the patch fits (factors >= 2 per axis)
+  constexpr int kPW = MW / 2 + 2, kPH = MH / 2 + 2;
+  __shared__ R ys[POST ? kPW * kPH : 1];
+  int pI = 0, pJ = 0, PW = 0;
+  bool staged = false;
   if (POST) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
+    int a0, a1, b0, b1;
+    R u0, u1;
+    ext_weights<R>(rx0, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+    pI = a0;
+    ext_weights<R>(rx0 + RW - 1, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+    PW = a1 - pI + 1;
+    ext_weights<R>(ry0, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+    pJ = b0;
+    ext_weights<R>(ry0 + RH - 1, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+    const int PH = b1 - pJ + 1;
+    staged = PW <= kPW && PH <= kPH;  // the same for every thread
+    if (staged) {
+      for (int e = threadIdx.x; e < PW * PH; e += BX * BY) {
+        const int jj = e / PW, ii = e - jj * PW;
+        ys[e] = y[(pI + ii) + X.cnx * (pJ + jj)];
+      }
+      __syncthreads();
+    }
   }
+  auto yv = [&](int I, int J) { return staged ? ys[(J - pJ) * PW + (I - pI)] : y[I + X.cnx * J]; };
   R cw[NR][2], ce[NR][2], cs[NR][2], cn[NR][2], dg[NR][2], rr[NR][2];
 #pragma unroll
   for (int b = 0; b < NR; ++b) {
@@ -81,12 +106,12 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
           // same products, in the same order, as the grid-wide prolongation
           R v = R(0);
           if (wj0 != R(0)) {
-            if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * y[xI0[q] + X.cnx * J0];
-            if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * y[xI1[q] + X.cnx * J0];
+            if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * yv(xI0[q], J0);
+            if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * yv(xI1[q], J0);
           }
           if (wj1 != R(0)) {
-            if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * y[xI0[q] + X.cnx * J1];
-            if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * y[xI1[q] + X.cnx * J1];
+            if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * yv(xI0[q], J1);
+            if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * yv(xI1[q], J1);
           }
           zc[c][lj][k] = zin[i + nx * j] + v;
         }
