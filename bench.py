@@ -161,7 +161,7 @@ def main():
         t = prob.small_timing
         avg_us = t["total_ms"] * 1e3 / max(t["launches"], 1)
         achieved = t["flops"] / (t["total_ms"] * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "k_small_2d<double>: inner PCG of the last inner level "
+        roofline = {"bound": "alu", "kernel": "k_small_2x2<double>: inner PCG of the last inner level "
                     "with its dense coarsest solve, one workgroup", "achieved": round(achieved, 5),
                     "peak": round(PEAK_FP64_CU_TFLOPS, 5), "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_CU_TFLOPS, 4),
                     "traffic": None, "avg_us": round(avg_us, 3), "launches": t["launches"],
@@ -170,7 +170,7 @@ def main():
                     "peak_basis": "FP64 vector peak of one CU: 78.6 TFLOP/s / 256 CUs (a one-workgroup kernel "
                                   "occupies one CU)"}
     if roofline:
-        print(f"[bench] dominant kernel k_small_2d: {roofline['avg_us']:.1f} us/launch over {roofline['launches']} "
+        print(f"[bench] dominant kernel k_small_2x2: {roofline['avg_us']:.1f} us/launch over {roofline['launches']} "
               f"launches, {roofline['achieved'] * 1e3:.1f} GFLOP/s = {roofline['frac']:.3f} of one CU's FP64 peak, "
               f"{roofline['share_of_step']:.2f} of the step", flush=True)
     # grid-wide kernels against HBM: the finest-level smoothers and SpMV

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmscg.so")
-SOURCES = ["mscg_kernels.hip", "mscg_small.hip", "mscg_small2d.hip", "mscg_smooth.hip", "mscg_engine.hip"]
+SOURCES = ["mscg_kernels.hip", "mscg_small.hip", "mscg_small2d.hip", "mscg_small2x2.hip", "mscg_smooth.hip", "mscg_engine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

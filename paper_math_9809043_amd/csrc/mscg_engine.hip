@@ -194,7 +194,7 @@ struct mscg_problem {
   bool ready;
   bool tiled;         // 2-D levels smooth with the tiled kernel
   int tile_shape;     // its tile shape (-1: by level size)
-  int small_variant;  // one-workgroup kernel of 2-D small levels (0 colour-split, 1 cell-strided)
+  int small_variant;  // one-workgroup kernel of 2-D small levels (0 2x2-block, else colour-split; 1 cell-strided; 2 colour-split)
   // per-solve state
   double eps2;
   double tol_scale;   // mixed: 1 / |r|^2 of the current outer iteration

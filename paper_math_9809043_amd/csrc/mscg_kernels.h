@@ -67,7 +67,8 @@ struct SmallDesc {
   int ncoarse;
   long long *iters, *calls;
   int* status;
-  int variant;  // one-workgroup kernel for 2-D levels: 0 colour-split, 1 cell-strided
+  int variant;  // one-workgroup kernel for 2-D levels: 0 2x2-block where it fits, else colour-split;
+                // 1 cell-strided; 2 colour-split
   const int* gate;  // see the gate of the grid-wide kernels
 };
 
@@ -143,6 +144,11 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s);
 // split LDS layout); hipErrorNotSupported otherwise.
 template <typename R>
 hipError_t launch_small_2d(const SmallDesc<R>& d, hipStream_t s);
+
+// The same for a 2-D level of at most 64 x 64 cells, one 2 x 2 block of cells
+// per thread with the iterate in registers; hipErrorNotSupported otherwise.
+template <typename R>
+hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s);
 
 // m symmetric Gauss-Seidel steps (2m+1 red-black half sweeps) on a 2-D level,
 // temporally blocked in LDS.  X == nullptr: pre-smoothing from zero into zout;

@@ -305,8 +305,9 @@ __global__ void __launch_bounds__(kThreads, 1) k_small_reg(RegArgs a) {
 
 template <typename R>
 hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
-  // 2-D levels go to the colour-split kernel (both precisions), the rest to
-  // the cell-strided kernel below.
+  // 2-D levels go to the 2x2-block kernel where they fit, else to the
+  // colour-split kernel (both precisions); the rest to the cell-strided kernel
+  // below.
   const int ks = d.ks, L = d.nlev - 1;
   if (ks + 1 != L) return hipErrorNotSupported;
   const Lv<R>& V = d.L[ks];
@@ -315,6 +316,10 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
   const int nc = X.cnx * X.cny * X.cnz;
   if (nc > 1024) return hipErrorNotSupported;
   if (d.variant == 0) {
+    const hipError_t e = launch_small_2x2<R>(d, s);
+    if (e != hipErrorNotSupported) return e;
+  }
+  if (d.variant == 0 || d.variant == 2) {
     const hipError_t e = launch_small_2d<R>(d, s);
     if (e != hipErrorNotSupported) return e;
   }

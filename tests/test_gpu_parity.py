@@ -280,14 +280,17 @@ def test_tiled_smoother_matches_half_sweeps(name, make, opt, monkeypatch):
     ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
     ("rect288x160", lambda: synth.smoothed_lognormal_2d(7, 288, 160, lo=-3, hi=3), {}),
     ("smooth256_const", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"interp": 1}),
-], ids=["smooth256", "rect288x160", "smooth256_const"])
+    # last inner level 56 x 40: part of the 64 x 64 block grid is ghosts
+    ("rect224x160", lambda: synth.smoothed_lognormal_2d(8, 224, 160, lo=-3, hi=3), {}),
+], ids=["smooth256", "rect288x160", "smooth256_const", "rect224x160"])
 def test_small_level_kernels_agree(name, make, opt, monkeypatch):
-    """The colour-split and the cell-strided one-workgroup solvers of the last
-    inner level give the same solve up to rounding, and both match the oracle."""
+    """The 2x2-block, the colour-split and the cell-strided one-workgroup
+    solvers of the last inner level give the same solve up to rounding, and
+    all match the oracle."""
     P = make()
     ref = oracle.solve(P, **oracle_opts(opt))
     out = {}
-    for variant in ("0", "1"):
+    for variant in ("0", "1", "2"):
         case(f"small-level kernel {variant} {name}")
         monkeypatch.setenv("MSCG_SMALL_VARIANT", variant)
         st, x, prob = gpu_solve(P, **opt)
@@ -296,7 +299,8 @@ def test_small_level_kernels_agree(name, make, opt, monkeypatch):
         assert abs(st.outer_iters - ref.outer_iters) <= 2
         assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) <= 1e-8
         out[variant] = x
-    assert np.linalg.norm(out["0"] - out["1"]) / np.linalg.norm(out["1"]) <= 1e-8
+    for v in ("0", "2"):
+        assert np.linalg.norm(out[v] - out["1"]) / np.linalg.norm(out["1"]) <= 1e-8
 
 
 SEMI_CASES = [
@@ -304,6 +308,8 @@ SEMI_CASES = [
     ("layered32_const", lambda: synth.layered_3d(3, 32, n_layers=8), (1, 1, 0.01), {"interp": 1}),
     ("strip256x64", lambda: synth.anisotropic_strip_2d(1, 256, 64), (1, 100, 1), {}),
     ("strip512x128", lambda: synth.anisotropic_strip_2d(4, 512, 128), (1, 100, 1), {}),
+    # last inner level 64 x 33 (y not coarsened): an odd side, ghost cells inside 2x2 blocks
+    ("strip256x132", lambda: synth.anisotropic_strip_2d(2, 256, 132), (1, 100, 1), {}),
     # the bench's 3-D workload at full size.  Its layers (contrast 1e6, kz = kx/100)
     # make the operator ill-conditioned enough that two iterates with relative
     # residual 1e-10 differ by ~1e-7, so both sides solve to 1e-12 here
