@@ -143,7 +143,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   add((size_t)P->lv[0].n * 8);  // b
   const size_t nc = (size_t)P->lv[nl - 1].n;
   add(nc * nc * 8); add(nc * nc * 8); add(nc * nc * 8);  // A (then its factor), row-major factor, A^-1
-  add((size_t)kMaxPartials * 8);
+  add((size_t)kPartSlots * 8);
   add(64);                                              // flags
   add(2 * MSCG_MAX_LEVELS * sizeof(long long));         // small-kernel counters
   P->bytes = b;
@@ -194,6 +194,7 @@ struct mscg_problem {
   bool ready;
   bool tiled;         // 2-D levels smooth with the tiled kernel
   int tile_shape;     // its tile shape (-1: by level size)
+  bool fuse_dot;      // the tiled post-smoother also forms the CG's r . z
   int small_variant;  // one-workgroup kernel of 2-D small levels (0 2x2-block, else colour-split; 1 cell-strided; 2 colour-split)
   // per-solve state
   double eps2;
@@ -332,10 +333,11 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
 // holds M_k^-1 r_k.  q is not touched, so the flexible beta can still use it.
 template <typename R>
 R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, R* const* xs, R* const* rs,
-                R* const* zs, R* const* ps, R* const* qs, int* rc, const int* gate) {
+                R* const* zs, R* const* ps, R* const* qs, int* rc, const int* gate, int* nfused) {
   const int m = P->o.smooth_steps;
   const Xfer X = xfer(P, k);
   *rc = MSCG_OK;
+  if (nfused) *nfused = 0;
   auto chk = [&](hipError_t e) {
     if (e != hipSuccess && *rc == MSCG_OK) *rc = fail(MSCG_E_DEVICE, "precond level %d: %s", k, hipGetErrorString(e));
     return e == hipSuccess;
@@ -380,7 +382,17 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
   *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs, gate);
   if (*rc) return nullptr;
   if (tiled) {
-    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->tile_shape, P->stream, gate))) return nullptr;
+    // the post-smoother also leaves the CG's r . z in per-tile partials
+    double* fpart = nullptr;
+    if (nfused && P->fuse_dot && !P->o.flexible) {
+      const int nt = smooth_tile_count(L.nx, L.ny, P->tile_shape);
+      if (nt <= kPartSlots) {
+        fpart = P->part;
+        *nfused = nt;
+      }
+    }
+    if (!chk(launch_smooth_tile<R>(L, &X, r, z, xs[k + 1], w, m, P->tile_shape, P->stream, gate, fpart)))
+      return nullptr;
     return w;
   }
   if (!chk(launch_prolong<R>(L, X, xs[k + 1], z, P->stream, gate))) return nullptr;
@@ -402,14 +414,16 @@ void vec_tables(mscg_problem* P, R** xs, R** rs, R** zs, R** ps, R** qs) {
 }
 
 // Applies the level-k preconditioner to the level's residual; *out receives
-// the vector (in the level's CG precision) that holds the result.
-int apply_prec(mscg_problem* P, int k, void** out, const int* gate) {
+// the vector (in the level's CG precision) that holds the result.  With
+// nfused, *nfused > 0 says that P->part holds that many partials of r . out.
+int apply_prec(mscg_problem* P, int k, void** out, const int* gate, int* nfused = nullptr) {
+  if (nfused) *nfused = 0;
   int rc = MSCG_OK;
   if (!mixed(P)) {
     double *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
     vec_tables<double>(P, xs, rs, zs, ps, qs);
     LevelH& H = P->lev[k];
-    *out = precond_host<double>(P, k, lv64(P, k), H.r, H.z, H.w, xs, rs, zs, ps, qs, &rc, gate);
+    *out = precond_host<double>(P, k, lv64(P, k), H.r, H.z, H.w, xs, rs, zs, ps, qs, &rc, gate, nfused);
     return rc;
   }
   float *xs[MSCG_MAX_LEVELS], *rs[MSCG_MAX_LEVELS], *zs[MSCG_MAX_LEVELS], *ps[MSCG_MAX_LEVELS], *qs[MSCG_MAX_LEVELS];
@@ -419,21 +433,23 @@ int apply_prec(mscg_problem* P, int k, void** out, const int* gate) {
     // the inner solves only need the overall accuracy; the outer CG recovers FP64)
     LevelH& L0 = P->lev[0];
     HIP_TRY(launch_scale_to_f32(L0.r, L0.r32, L0.n, L0.sc, P->stream));
-    float* z32 = precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc, nullptr);
+    float* z32 =
+        precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc, nullptr, nullptr);
     if (rc) return rc;
     HIP_TRY(launch_scale_to_f64(z32, L0.z, L0.n, L0.sc, P->stream));
     *out = L0.z;
     return MSCG_OK;
   }
   LevelH& H = P->lev[k];
-  *out = precond_host<float>(P, k, lv32(P, k), H.r32, H.z32, H.w32, xs, rs, zs, ps, qs, &rc, gate);
+  *out = precond_host<float>(P, k, lv32(P, k), H.r32, H.z32, H.w32, xs, rs, zs, ps, qs, &rc, gate, nfused);
   return rc;
 }
 
 // One level's CG loop (Templates Figure 2.5) on vectors of type R; the residual
 // is in r_k and the entry check has been done (sc->converged).  Per iteration:
 // the preconditioner, r.z, p and A p with p.q, then the x / r update with
-// |r|^2, each reduction followed by its one-workgroup finish.  The directions
+// |r|^2, each reduction followed by its one-workgroup finish (r.z comes as
+// per-tile partials from the tiled post-smoother where that runs).  The directions
 // alternate between p and p2 (the next one is formed from the current one on
 // the fly, inside the SpMV).
 //
@@ -457,12 +473,16 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p
     if (ahead) batch = std::max(1, std::min(queued == 0 ? P->spec_hint[k] + 1 : 2, max_iter - queued));
     for (int b = 0; b < batch; ++b, ++queued) {
       void* zres = nullptr;
-      rc = apply_prec(P, k, &zres, gate);
+      int nfused = 0;
+      rc = apply_prec(P, k, &zres, gate, &nfused);
       if (rc) return rc;
       z = static_cast<R*>(zres);
       if (P->o.flexible && queued > 0)
         HIP_TRY(launch_dot_fin<R>(z, q, L.n, P->part, nb, H.sc, kOpZq, P->stream, gate));
-      HIP_TRY(launch_dot_fin<R>(r, z, L.n, P->part, nb, H.sc, kOpRho, P->stream, gate));
+      if (nfused)
+        HIP_TRY(launch_finish(P->part, nfused, H.sc, kOpRho, P->stream, gate));
+      else
+        HIP_TRY(launch_dot_fin<R>(r, z, L.n, P->part, nb, H.sc, kOpRho, P->stream, gate));
       HIP_TRY(launch_pspmv_fin<R>(L, z, pc, pn, q, P->part, nb, H.sc, P->stream, gate));
       HIP_TRY(launch_cg_update_fin<R>(x, r, pn, q, L.n, P->part, nb, H.sc, P->stream, gate));
       std::swap(pc, pn);
@@ -557,7 +577,7 @@ int carve(mscg_problem* P, const Plan& plan) {
   P->Lrows = (double*)take(nc * nc * 8);
   P->Ainv = (double*)take(nc * nc * 8);
   P->ncoarse = (int)nc;
-  P->part = (double*)take((size_t)kMaxPartials * 8);
+  P->part = (double*)take((size_t)kPartSlots * 8);
   P->dflags = (int*)take(64);
   P->dcount = (long long*)take(2 * MSCG_MAX_LEVELS * sizeof(long long));
   if (off > P->ws_bytes) return fail(MSCG_E_NOMEM, "workspace carving overflow");
@@ -675,6 +695,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   {
     const char* e = getenv("MSCG_UNTILED");
     P->tiled = !(e && e[0] == '1');
+    const char* fd = getenv("MSCG_FUSED_DOT");
+    P->fuse_dot = !(fd && fd[0] == '0');
     const char* t = getenv("MSCG_TILE_SHAPE");
     P->tile_shape = t ? atoi(t) : -1;
     const char* v = getenv("MSCG_SMALL_VARIANT");

@@ -9,6 +9,7 @@
 namespace mscg {
 
 constexpr int kMaxPartials = 1024;  // blocks of a grid-wide reduction
+constexpr int kPartSlots = 8192;    // partials the workspace holds (the tiled post-smoother's r . z per tile)
 
 // Device-resident scalars of one level's CG (Templates Figure 2.5).
 struct Scal {
@@ -78,7 +79,7 @@ hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s);
 hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
                                 hipStream_t s);
-hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s);
+hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s, const int* gate = nullptr);
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
 hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp, hipStream_t s);
 hipError_t launch_scale_to_f32(const double* a, float* b, int n, const Scal* sc, hipStream_t s);
@@ -155,11 +156,13 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s);
 // otherwise post-smoothing from zin + E y into zout (zout must not alias zin).
 // Tiles are built for m = 4; smooth_tile_supported says whether a level can use
 // them (hipErrorNotSupported otherwise).  shape: tile shape 0..3, or -1 to
-// choose by the level size.
+// choose by the level size.  With part (post-smoothing only), tile t also
+// writes part[t] = its share of r . zout, smooth_tile_count tiles in all.
 bool smooth_tile_supported(int nz, bool has_tz, int m);
+int smooth_tile_count(int nx, int ny, int shape);
 template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, int m,
-                              int shape, hipStream_t s, const int* gate = nullptr);
+                              int shape, hipStream_t s, const int* gate = nullptr, double* part = nullptr);
 
 // g = E^T (r - A z) on a 2-D level in one launch (factors s <= 4 per axis);
 // hipErrorNotSupported otherwise.  Same sums, in the same order, as

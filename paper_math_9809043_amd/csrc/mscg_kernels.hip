@@ -1078,8 +1078,8 @@ hipError_t launch_cg_update_fin(R* x, R* r, const R* p, const R* q, int n, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op, (const int*)nullptr);
+hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op, gate);
   return hipGetLastError();
 }
 

@@ -30,7 +30,8 @@ constexpr int kHalo = 9;  // 2m + 1 for m = 4
 template <typename R, bool POST, int TW, int TH, int BX, int BY>
 __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                          const R* __restrict__ zin, const R* __restrict__ y,
-                                                         R* __restrict__ zout, const int* __restrict__ gate) {
+                                                         R* __restrict__ zout, const int* __restrict__ gate,
+                                                         double* __restrict__ part) {
   if (gate && *gate) return;
   constexpr int MW = TW + 2 * kHalo, MH = TH + 2 * kHalo;
   constexpr int HW = (MW + 1) / 2;         // cells of one colour per region row, upper bound
@@ -159,20 +160,51 @@ __global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R
       if (li < RW && i >= x0 && i < x0 + TW) zout[i + nx * j] = zc[c][lj][k];
     }
   }
+  if (POST && part) {
+    // this tile's part of r . zout (the CG's rho), tile cells in thread
+    // order, then the waves in order: one partial per tile
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < NR; ++b) {
+      const int lj = ty + BY * b;
+      const int j = ry0 + lj;
+      if (lj >= RH || j < y0 || j >= y0 + TH) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int li = 2 * k + ((rx0 + ry0 + lj + c) & 1);
+        const int i = rx0 + li;
+        if (li < RW && i >= x0 && i < x0 + TW) acc += (double)rr[b][c] * (double)zc[c][lj][k];
+      }
+    }
+    __shared__ double wsum[BX * BY / kWave];
+    acc = wave_sum_dpp(acc);
+    const int tid = threadIdx.x;
+    if ((tid & (kWave - 1)) == kWave - 1) wsum[tid / kWave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < BX * BY / kWave; ++w) t += wsum[w];
+      part[blockIdx.x + gridDim.x * blockIdx.y] = t;
+    }
+  }
 }
 
 template <typename R, int TW, int TH, int BX, int BY>
 hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, hipStream_t s,
-                        const int* gate) {
+                        const int* gate, double* part) {
   const dim3 grid((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
   const dim3 block(BX * BY);
   if (X)
-    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout, gate);
+    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout, gate,
+                       part);
   else
     hipLaunchKernelGGL((k_smooth_tile<R, false, TW, TH, BX, BY>), grid, block, 0, s, L, Xfer{}, r, zin, y, zout,
-                       gate);
+                       gate, (double*)nullptr);
   return hipGetLastError();
 }
+
+constexpr int kShapeTW[4] = {64, 110, 46, 14}, kShapeTH[4] = {32, 38, 14, 14};
 
 // Tile shapes: 0 = 64 x 32 (512 threads), 1 = 110 x 38 (512 threads, region
 // rows of exactly 128 cells), 2 = 46 x 14 (256 threads), 3 = 14 x 14 (256
@@ -265,16 +297,21 @@ __global__ void __launch_bounds__(256) k_resid_restrict_tile(Lv<R> L, Xfer X, co
 
 bool smooth_tile_supported(int nz, bool has_tz, int m) { return nz == 1 && !has_tz && 2 * m + 1 == kHalo; }
 
+int smooth_tile_count(int nx, int ny, int shape) {
+  if (shape < 0 || shape > 3) shape = auto_shape(nx, ny);
+  return ((nx + kShapeTW[shape] - 1) / kShapeTW[shape]) * ((ny + kShapeTH[shape] - 1) / kShapeTH[shape]);
+}
+
 template <typename R>
 hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout,
-                              int m, int shape, hipStream_t s, const int* gate) {
+                              int m, int shape, hipStream_t s, const int* gate, double* part) {
   if (!smooth_tile_supported(L.nz, L.tz != nullptr, m)) return hipErrorNotSupported;
   if (shape < 0 || shape > 3) shape = auto_shape(L.nx, L.ny);
   switch (shape) {
-    case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate);
-    case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate);
-    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s, gate);
-    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate);
+    case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
+    case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
+    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s, gate, part);
+    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate, part);
   }
 }
 
@@ -299,8 +336,8 @@ template hipError_t launch_resid_restrict_tile<float>(const Lv<float>&, const Xf
                                                      float*, hipStream_t, const int*);
 
 template hipError_t launch_smooth_tile<double>(const Lv<double>&, const Xfer*, const double*, const double*,
-                                               const double*, double*, int, int, hipStream_t, const int*);
+                                               const double*, double*, int, int, hipStream_t, const int*, double*);
 template hipError_t launch_smooth_tile<float>(const Lv<float>&, const Xfer*, const float*, const float*,
-                                              const float*, float*, int, int, hipStream_t, const int*);
+                                              const float*, float*, int, int, hipStream_t, const int*, double*);
 
 }  // namespace mscg

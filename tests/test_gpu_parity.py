@@ -261,6 +261,8 @@ def test_tiled_smoother_matches_half_sweeps(name, make, opt, monkeypatch):
     half sweeps bitwise (a missing barrier, a short halo or a wrong ragged
     tile edge would break this)."""
     P = make()
+    # r . z from the same grid-wide reduction on both sides
+    monkeypatch.setenv("MSCG_FUSED_DOT", "0")
     monkeypatch.setenv("MSCG_UNTILED", "1")
     case(f"untiled {name}")
     st_u, x_u, _ = gpu_solve(P, **opt)
@@ -274,6 +276,29 @@ def test_tiled_smoother_matches_half_sweeps(name, make, opt, monkeypatch):
         st_t, x_t, _ = gpu_solve(P, **opt)
         assert st_t.level_iters == st_u.level_iters
         assert np.array_equal(x_t, x_u), (shape, np.abs(x_t - x_u).max())
+
+
+@pytest.mark.parametrize("name,make,opt", [
+    ("ragged96x40", lambda: synth.smoothed_lognormal_2d(4, 96, 40, lo=-3, hi=3), {}),
+    ("smooth512", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {}),
+    ("smooth512_mixed", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {"precision": 1}),
+], ids=["ragged96x40", "smooth512", "smooth512_mixed"])
+def test_fused_rho_matches_grid_wide_dot(name, make, opt, monkeypatch):
+    """r . z summed per tile by the post-smoother (one partial per tile) gives
+    the solve of the grid-wide reduction up to rounding, and matches the oracle."""
+    P = make()
+    ref = oracle.solve(P)
+    out = {}
+    for fused in ("0", "1"):
+        case(f"fused r.z {fused} {name}")
+        monkeypatch.setenv("MSCG_FUSED_DOT", fused)
+        st, x, _ = gpu_solve(P, **opt)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
+        assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) <= 1e-8
+        out[fused] = (st, x)
+    assert abs(out["0"][0].outer_iters - out["1"][0].outer_iters) <= 1
+    assert np.linalg.norm(out["0"][1] - out["1"][1]) / np.linalg.norm(out["0"][1]) <= 1e-9
 
 
 @pytest.mark.parametrize("name,make,opt", [
