@@ -12,6 +12,7 @@ namespace {
 
 constexpr int kBlock = 256;
 #define MSCG_COARSE_CAP 1024  // largest coarsest level (LDS of the inverse kernel)
+constexpr size_t kBandLds = 144 * 1024;  // LDS of the in-LDS band factorisation and inverse
 // dynamic LDS of the small-level solver: 160 KB per CU minus its static arrays
 constexpr size_t kSmallLdsBytes = 140 * 1024;
 
@@ -307,6 +308,70 @@ __global__ void __launch_bounds__(1024) k_chol_band(const double* __restrict__ A
     for (int t = tid; t < W; t += nt) win[sj * W + t] = row_entry(j + W, t);
     __syncthreads();
   }
+  if (tid == 0) status[0] = bad;
+}
+
+// Entry A[i][i + off] (-b <= off <= 0) of the 5/7-point operator, with the
+// sums of k_dense_assemble in the same order.
+__device__ double band_entry(const Lv<double>& L, int c, int off) {
+  int i, j, k;
+  cell_ijk(c, L.nx, L.ny, i, j, k);
+  const int fx = i + (L.nx + 1) * (j + L.ny * k), fy = i + L.nx * (j + (L.ny + 1) * k);
+  const int plane = L.nx * L.ny;
+  if (off == 0) {
+    double d = L.tx[fx] + L.tx[fx + 1] + L.ty[fy] + L.ty[fy + L.nx];
+    if (L.tz) {
+      const int fz = i + L.nx * j + plane * k;
+      d += L.tz[fz] + L.tz[fz + plane];
+    }
+    return d;
+  }
+  if (off == -1 && i > 0) return -L.tx[fx];
+  if (off == -L.nx && j > 0) return -L.ty[fy];
+  if (L.tz && off == -plane && k > 0) return -L.tz[i + L.nx * j + plane * k];
+  return 0.0;
+}
+
+// The same banded factorisation with the whole band in LDS (n (b + 1)
+// doubles), assembled there from the transmissibilities: a step reads and
+// writes LDS only, with no wait on memory.  Row i of the band holds
+// A[i][i - b + t] and, once the steps before i are done, L[i][i - b + t].
+// Same operations, in the same order, as k_chol_band.
+__global__ void __launch_bounds__(256) k_chol_band_lds(Lv<double> L, int b, double* __restrict__ Lb,
+                                                       double* __restrict__ Lt, int* __restrict__ status) {
+  extern __shared__ double band[];
+  const int n = L.n, W = b + 1, tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < n * W; e += nt) {
+    const int i = e / W, t = e - i * W;
+    band[e] = i - b + t >= 0 ? band_entry(L, i, t - b) : 0.0;
+  }
+  __syncthreads();
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    const double djj = band[j * W + b];
+    if (!(djj > 0.0)) { bad = 1; break; }  // every thread reads the same value
+    const double ljj = sqrt(djj);
+    for (int t = tid; t < b; t += nt) {
+      const int i = j + 1 + t;
+      if (i < n) band[i * W + (b - 1 - t)] /= ljj;
+    }
+    __syncthreads();  // every thread has read band[j][b]
+    if (tid == 0) band[j * W + b] = ljj;
+    for (int e = tid; e < b * b; e += nt) {
+      const int ii = e / b, kk = e - ii * b;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      if (i >= n) continue;
+      band[i * W + (k - i + b)] -= band[i * W + (j - i + b)] * band[k * W + (j - k + b)];
+    }
+    __syncthreads();
+  }
+  if (!bad)
+    for (int e = tid; e < n * W; e += nt) {
+      const int i = e / W, t = e - i * W;
+      Lb[e] = band[e];
+      Lt[e] = i + t < n ? band[(i + t) * W + (b - t)] : 0.0;
+    }
   if (tid == 0) status[0] = bad;
 }
 
@@ -954,21 +1019,87 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s) 
   return hipGetLastError();
 }
 
+// k_band_inverse with both bands of the factor in LDS for the whole launch
+// (2 n (b + 1) doubles) and each wave's column in LDS: no barriers between
+// rows.  Same operations, in the same order.
+__global__ void __launch_bounds__(256) k_band_inverse_lds(const double* __restrict__ Lb, const double* __restrict__ Lt,
+                                                          double* __restrict__ Ainv, int n, int b) {
+  extern __shared__ double sh[];
+  const int W = b + 1;
+  double* lb = sh;
+  double* lt = sh + (long long)n * W;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* w = sh + 2LL * n * W + (long long)wave * n;
+  for (int e = threadIdx.x; e < n * W; e += blockDim.x) {
+    lb[e] = Lb[e];
+    lt[e] = Lt[e];
+  }
+  const int c = blockIdx.x * 4 + wave;
+  for (int k = lane; k < n; k += kWave) w[k] = 0.0;
+  __syncthreads();
+  if (c >= n) return;
+  double reg = 0.0;
+  for (int i = c; i < n; ++i) {
+    const int d = (lane - i) & (kWave - 1), k = i - kWave + d;
+    const double term = (k >= c && k >= i - b) ? lb[i * W + (k - i + b)] * reg : 0.0;
+    const double s = wave_total(term);
+    const double wi = ((i == c ? 1.0 : 0.0) - s) / lb[i * W + b];
+    if ((i & (kWave - 1)) == lane) {
+      reg = wi;
+      w[i] = wi;
+    }
+  }
+  reg = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const int k = i + 1 + ((lane - i - 1) & (kWave - 1));
+    const double term = (k <= i + b && k < n) ? lt[i * W + (k - i)] * reg : 0.0;
+    const double s = wave_total(term);
+    const double xi = (w[i] - s) / lt[i * W];
+    if ((i & (kWave - 1)) == lane) {
+      reg = xi;
+      w[i] = xi;
+    }
+  }
+  for (int k = lane; k < n; k += kWave) Ainv[(long long)c * n + k] = w[k];
+}
+
 hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
                                 hipStream_t s) {
   if (L.n > MSCG_COARSE_CAP) return hipErrorInvalidValue;
   const long long nn = (long long)L.n * L.n;
-  hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
   // bandwidth in natural order; the two band copies of the factor go to Lrows
   const int b = L.nz > 1 ? L.nx * L.ny : (L.ny > 1 ? L.nx : 1);
   if (b <= 64 && 2LL * (b + 1) * L.n <= nn) {
+    // factor and inverse each with their band in LDS where it fits
     const int W = b + 1;
-    hipLaunchKernelGGL(k_chol_band, dim3(1), dim3(1024), (size_t)W * W * sizeof(double), s, A, L.n, b, Lrows,
-                       Lrows + (long long)L.n * W, status);
-    hipLaunchKernelGGL(k_band_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, Lrows, Lrows + (long long)L.n * W,
-                       Ainv, L.n, b);
+    const size_t f_lds = (size_t)L.n * W * sizeof(double);
+    const size_t i_lds = (2 * (size_t)L.n * W + 4 * (size_t)L.n) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_chol_band_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)kBandLds);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_band_inverse_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kBandLds);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    double* Lb = Lrows;
+    double* Lt = Lrows + (long long)L.n * W;
+    if (f_lds <= kBandLds) {
+      hipLaunchKernelGGL(k_chol_band_lds, dim3(1), dim3(256), f_lds, s, L, b, Lb, Lt, status);
+    } else {
+      hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
+      hipLaunchKernelGGL(k_chol_band, dim3(1), dim3(1024), (size_t)W * W * sizeof(double), s, A, L.n, b, Lb, Lt,
+                         status);
+    }
+    if (i_lds <= kBandLds)
+      hipLaunchKernelGGL(k_band_inverse_lds, dim3((L.n + 3) / 4), dim3(256), i_lds, s, Lb, Lt, Ainv, L.n, b);
+    else
+      hipLaunchKernelGGL(k_band_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, Lb, Lt, Ainv, L.n, b);
     return hipGetLastError();
   }
+  hipLaunchKernelGGL(k_dense_assemble, dim3((L.n + 255) / 256), dim3(256), 0, s, L, A);
   hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(1024), 0, s, A, L.n, status);
   hipLaunchKernelGGL(k_factor_rows, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, Lrows, L.n);
   hipLaunchKernelGGL(k_chol_inverse, dim3((L.n + 3) / 4), dim3(256), 0, s, A, Lrows, Ainv, L.n);

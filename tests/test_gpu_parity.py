@@ -180,12 +180,16 @@ def test_solve_parity(name, make, opt):
     assert np.linalg.norm(Ax - b) / np.linalg.norm(b) <= 1.5e-10
 
 
-def test_single_level_direct_solve():
-    case("solve single level 16x16 direct")
-    P = synth.smoothed_lognormal_2d(2, 16)
-    st, x, prob = gpu_solve(P)
+@pytest.mark.parametrize("side,opt", [(16, {}), (24, {"max_levels": 1}), (32, {"max_levels": 1})],
+                         ids=["16x16", "24x24", "32x32"])
+def test_single_level_direct_solve(side, opt):
+    """One level, solved by the coarsest factorisation and inverse alone: band
+    in LDS (16 x 16, 24 x 24), band through a window (32 x 32)."""
+    case(f"solve single level {side}x{side} direct")
+    P = synth.smoothed_lognormal_2d(2, side)
+    st, x, prob = gpu_solve(P, **opt)
     assert prob.n_levels == 1 and st.outer_iters == 0
-    ref = oracle.solve(P)
+    ref = oracle.solve(P, **oracle_opts(opt))
     assert np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p) < 1e-10
 
 
