@@ -590,6 +590,19 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restric
   y[i] = (R)s;
 }
 
+// Keeps a loaded value live at this point, so that a load whose result is only
+// needed after a gate's early return is still issued before it (the two
+// round trips to memory then overlap).
+template <typename T>
+__device__ __forceinline__ void issue_before(const T& v) {
+  asm volatile("" ::"s"(v));
+}
+
+// An ungated launch reads this instead of a flag: the gate's load then needs
+// no branch on the pointer first.
+__device__ const int g_no_gate = 0;
+__device__ __forceinline__ const int* gate_or_zero(const int* gate) { return gate ? gate : &g_no_gate; }
+
 // Scalar bookkeeping of one level's CG (Templates Figure 2.5) from the sum s
 // of a reduction; one thread.
 __device__ void apply_op(double s, Scal* __restrict__ sc, int op) {
@@ -643,10 +656,30 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 
 __global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
                                                    int op, const int* __restrict__ gate) {
-  if (gate && *gate) return;
+  // the gate, the scalars and (up to 8 per thread) the partials are read in
+  // one round trip; the sum keeps the order of sum_partials
+  const int gv = *gate_or_zero(gate);
+  Scal loc = *sc;
+  constexpr int kF = 8;
+  double pv[kF];
+#pragma unroll
+  for (int u = 0; u < kF; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    pv[u] = q < nparts ? part[q] : 0.0;
+  }
+  issue_before(gv);
+  issue_before(loc.rho);
+  if (gv) return;
+  double acc = pv[0];
+#pragma unroll
+  for (int u = 1; u < kF; ++u) acc += pv[u];
+  for (int q = threadIdx.x + kF * blockDim.x; q < nparts; q += blockDim.x) acc += part[q];
   __shared__ double sm[kBlock / kWave];
-  const double s = sum_partials(part, nparts, sm);
-  if (threadIdx.x == 0) apply_op(s, sc, op);
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) {
+    apply_op(s, &loc, op);
+    *sc = loc;
+  }
 }
 
 // partial sums of a . b (gated)
@@ -669,10 +702,16 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_pspmv(Lv<R> L, const R* __restrict__ z, const R* __restrict__ pold,
                                                    R* __restrict__ pnew, R* __restrict__ q, double* __restrict__ part,
                                                    const Scal* __restrict__ sc, const int* __restrict__ gate) {
-  if (gate && *gate) return;
+  const int gv = *gate_or_zero(gate);
+  const int it = sc->it;
+  const double beta_d = sc->beta;
+  issue_before(gv);
+  issue_before(it);
+  issue_before(beta_d);
+  if (gv) return;
   __shared__ double sm[kBlock / kWave];
-  const bool first = sc->it == 0;
-  const R beta = (R)sc->beta;
+  const bool first = it == 0;
+  const R beta = (R)beta_d;
   auto pv = [&](int c) { return first ? z[c] : z[c] + beta * pold[c]; };
   double acc = 0.0;
   const int nx = L.nx, ny = L.ny;
@@ -712,9 +751,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_update_g(R* __restrict__ x, R* __
                                                          const R* __restrict__ p, const R* __restrict__ q, int n,
                                                          double* __restrict__ part, const Scal* __restrict__ sc,
                                                          const int* __restrict__ gate) {
-  if (gate && *gate) return;
+  const int gv = *gate_or_zero(gate);
+  const double alpha_d = sc->alpha;
+  issue_before(gv);
+  issue_before(alpha_d);
+  if (gv) return;
   __shared__ double sm[kBlock / kWave];
-  const R alpha = (R)sc->alpha;
+  const R alpha = (R)alpha_d;
   double acc = 0.0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     x[c] += alpha * p[c];
