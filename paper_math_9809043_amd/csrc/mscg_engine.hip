@@ -172,6 +172,8 @@ struct mscg_problem {
   int nlev, ks;
   LevelH lev[MSCG_MAX_LEVELS];
   double *Atmp, *Lrows, *Ainv;
+  const double* Asym;  // packed lower triangle of Ainv (in Atmp), or null
+  int ntile;
   int ncoarse;
   double* part;
   double* b;
@@ -195,6 +197,7 @@ struct mscg_problem {
   bool tiled;         // 2-D levels smooth with the tiled kernel
   int tile_shape;     // its tile shape (-1: by level size)
   bool fuse_dot;      // the tiled post-smoother also forms the CG's r . z
+  bool sym_coarse;    // one-workgroup solvers apply the coarsest inverse from its lower triangle
   int small_variant;  // one-workgroup kernel of 2-D small levels (0 2x2-block, else colour-split; 1 cell-strided; 2 colour-split)
   // per-solve state
   double eps2;
@@ -310,6 +313,8 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
     d.max_inner = P->o.max_inner_iters;
     d.rel_floor2 = mixed(P) ? P->o.inner_rel_floor * P->o.inner_rel_floor : 0.0;
     d.Ainv = P->Ainv;
+    d.Asym = P->Asym;
+    d.ntile = P->ntile;
     d.ncoarse = P->ncoarse;
     d.iters = P->dcount;
     d.calls = P->dcount + MSCG_MAX_LEVELS;
@@ -697,6 +702,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
     P->tiled = !(e && e[0] == '1');
     const char* fd = getenv("MSCG_FUSED_DOT");
     P->fuse_dot = !(fd && fd[0] == '0');
+    const char* sy = getenv("MSCG_SYM_COARSE");
+    P->sym_coarse = !(sy && sy[0] == '0');
     const char* t = getenv("MSCG_TILE_SHAPE");
     P->tile_shape = t ? atoi(t) : -1;
     const char* v = getenv("MSCG_SMALL_VARIANT");
@@ -775,6 +782,17 @@ int mscg_set_permeability(mscg_problem* P, const double* kx, const double* ky, c
   }
   // coarsest factorisation
   HIP_TRY(launch_coarse_factor(lv64(P, P->nlev - 1), P->Atmp, P->Lrows, P->Ainv, P->dflags, P->stream));
+  // the lower triangle of the inverse in 16 x 16 tiles for the one-workgroup
+  // solvers, in the factorisation's scratch (free from here on)
+  P->Asym = nullptr;
+  {
+    const int nc = P->ncoarse, nt = (nc + 15) / 16;
+    if (P->sym_coarse && nc <= 256 && (long long)nt * (nt + 1) / 2 * 256 <= (long long)nc * nc) {
+      HIP_TRY(launch_pack_sym(P->Ainv, nc, nt, P->Atmp, P->stream));
+      P->Asym = P->Atmp;
+      P->ntile = nt;
+    }
+  }
   HIP_TRY(hipMemcpyAsync(P->hflags, P->dflags, 16, hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   if (P->hflags[0]) {

@@ -1106,6 +1106,23 @@ __global__ void __launch_bounds__(256) k_band_inverse_lds(const double* __restri
   for (int k = lane; k < n; k += kWave) Ainv[(long long)c * n + k] = w[k];
 }
 
+__global__ void k_pack_sym(const double* __restrict__ Ainv, int n, int NT, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NT * (NT + 1) / 2 * 256) return;
+  const int t = e >> 8, r = (e >> 4) & 15, c = e & 15;
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int J = t - I * (I + 1) / 2;
+  const int i = 16 * I + r, j = 16 * J + c;
+  out[e] = i < n && j < n ? Ainv[(long long)i * n + j] : 0.0;
+}
+
+hipError_t launch_pack_sym(const double* Ainv, int n, int ntile, double* out, hipStream_t s) {
+  const int tot = ntile * (ntile + 1) / 2 * 256;
+  hipLaunchKernelGGL(k_pack_sym, dim3((tot + 255) / 256), dim3(256), 0, s, Ainv, n, ntile, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
                                 hipStream_t s) {
   if (L.n > MSCG_COARSE_CAP) return hipErrorInvalidValue;

@@ -19,13 +19,16 @@
 // right-hand side and unit diagonal: they stay zero.
 //
 // The residual for the restriction goes to a natural-layout LDS array; the
-// restriction, the coarsest solve (dense FP64 inverse) and the prolongation
-// follow the colour-split kernel.  Reductions: the four owned cells in order,
-// DPP within each wave, then the 16 wave sums in order.
+// restriction and the prolongation follow the colour-split kernel.  The
+// coarsest solve applies the FP64 inverse from its lower triangle alone (the
+// inverse is symmetric), stored in 16 x 16 tiles: half the bytes the dense
+// product reads from L2 each iteration.  Reductions: the four owned cells in
+// order, DPP within each wave, then the 16 wave sums in order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "mscg_kernels.h"
 
@@ -39,7 +42,6 @@ constexpr int kEP = kBW + 2;           // exchange array pitch (zero border)
 constexpr int kEA = (kBH + 2) * kEP;   // entries per exchange array
 constexpr int kRP = 2 * kBW;           // residual array pitch
 constexpr int kFoot2 = 12;             // >= footprint of one coarse cell along an axis (linear, s <= 4)
-constexpr int kBatch2 = 8;             // inverse entries loaded per batch
 
 struct Small2x2Args {
   int nx, ny;
@@ -48,7 +50,8 @@ struct Small2x2Args {
   double tol, rel_floor2;
   const void *tx, *ty, *rhs;
   void* x;
-  const double* Ainv;
+  const double* Asym;  // lower triangle of the coarsest inverse in 16 x 16 tiles
+  int ntile;           // tiles per side
   long long *iters, *calls;
   int level;
   int* status;
@@ -202,9 +205,6 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
   long long iters = 0, coarse_calls = 0;
   int status = 0;
   double rho_old = 0.0;
-  const int half_nc = nc / 2;  // nc is even (checked at launch)
-  const int groups = kT / half_nc;
-  const int per = (nc + groups - 1) / groups;
 
   if (!(rr < tol)) {
     for (int it = 0; it < a.max_inner; ++it) {
@@ -243,32 +243,65 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
         g[e] = (double)s;
       }
       __syncthreads();
-      // -- coarsest: y = A^-1 g, thread (group, pair) over its column range
-      if (tid < groups * half_nc) {
-        const int ip = tid % half_nc, grp = tid / half_nc;
-        const int j0 = grp * per, j1 = min(j0 + per, nc);
-        double s0 = 0.0, s1 = 0.0;
-        for (int jb = j0; jb < j1; jb += kBatch2) {
-          double2 av[kBatch2];
-#pragma unroll
-          for (int t = 0; t < kBatch2; ++t)
-            av[t] = jb + t < j1 ? *reinterpret_cast<const double2*>(a.Ainv + (long long)(jb + t) * nc + 2 * ip)
-                               : make_double2(0.0, 0.0);
-#pragma unroll
-          for (int t = 0; t < kBatch2; ++t)
-            if (jb + t < j1) {
-              s0 += av[t].x * g[jb + t];
-              s1 += av[t].y * g[jb + t];
-            }
+      {
+        // -- coarsest: y = A^-1 g from the lower triangle in 16 x 16 tiles.
+        // A 16-lane group (one DPP row) takes tile (I, J), I >= J, lane c
+        // its column c: y_J[c] += sum_r T[r][c] g_I[r] stays in the lane,
+        // y_I[r] += sum_c T[r][c] g_J[c] is a sum across the lanes, formed
+        // by a four-stage exchange that leaves row c's total in lane c.
+        // Each output block gets one 16-vector per tile of its block row or
+        // column (slot = the other tile index), summed in slot order.
+        const int NT = a.ntile, ntiles = NT * (NT + 1) / 2;
+        const int grp = tid >> 4, c = tid & 15;
+        auto gat = [&](int e) { return e < nc ? g[e] : 0.0; };
+        for (int t = grp; t < ntiles; t += kT / 16) {
+          int I = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+          while (I * (I + 1) / 2 > t) --I;
+          while ((I + 1) * (I + 2) / 2 <= t) ++I;
+          const int J = t - I * (I + 1) / 2;
+          const double* T = a.Asym + (long long)t * 256;
+          const double gJc = gat(16 * J + c);
+          // Rows arrive in quads (q, q + 8, q + 4, q + 12): the first two
+          // exchange stages (partners 15 - c, then 7 - (c mod 8) within the
+          // half row) run as they arrive, the third (3 - (c mod 4)) once
+          // quads q and q + 2 are in, so few partial rows are ever live.
+          const bool h8 = (c & 8) != 0, h4 = (c & 4) != 0, h2 = (c & 2) != 0, h1 = (c & 1) != 0;
+          const double gIc = gat(16 * I + c);  // lane k of the group hands g_I[k] to the others
+          double acc_c = 0.0;
+          auto xchg = [](bool hi, double lo_v, double hi_v, auto ctrl) {
+            constexpr int C = decltype(ctrl)::value;
+            return (hi ? hi_v : lo_v) + dpp_d<C, 0xf>(hi ? lo_v : hi_v);
+          };
+          auto quad = [&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const double a0 = T[q * 16 + c], a1 = T[(q + 8) * 16 + c];
+            const double a2 = T[(q + 4) * 16 + c], a3 = T[(q + 12) * 16 + c];
+            acc_c += a0 * dpp_d<0x150 + q, 0xf>(gIc);  // row_newbcast: lane r of the row
+            acc_c += a1 * dpp_d<0x150 + q + 8, 0xf>(gIc);
+            acc_c += a2 * dpp_d<0x150 + q + 4, 0xf>(gIc);
+            acc_c += a3 * dpp_d<0x150 + q + 12, 0xf>(gIc);
+            const double s0 = xchg(h8, a0 * gJc, a1 * gJc, std::integral_constant<int, 0x140>{});
+            const double s1 = xchg(h8, a2 * gJc, a3 * gJc, std::integral_constant<int, 0x140>{});
+            return xchg(h4, s0, s1, std::integral_constant<int, 0x141>{});
+          };
+          const double v0 = quad(std::integral_constant<int, 0>{});
+          const double v1 = quad(std::integral_constant<int, 1>{});
+          const double w0 = xchg(h2, v0, quad(std::integral_constant<int, 2>{}), std::integral_constant<int, 0x1B>{});
+          const double w1 = xchg(h2, v1, quad(std::integral_constant<int, 3>{}), std::integral_constant<int, 0x1B>{});
+          part[(J * NT + I) * 16 + c] = acc_c;
+          if (I != J) {  // the same for all 16 lanes of the group
+            // partner c xor 1: lane c ends with the total of row c
+            const double row = xchg(h1, w0, w1, std::integral_constant<int, 0xB1>{});
+            part[(I * NT + J) * 16 + c] = row;
+          }
         }
-        part[grp * nc + 2 * ip] = s0;
-        part[grp * nc + 2 * ip + 1] = s1;
-      }
-      __syncthreads();
-      for (int i = tid; i < nc; i += kT) {
-        double s = 0.0;
-        for (int grp = 0; grp < groups; ++grp) s += part[grp * nc + i];
-        y[i] = s;
+        __syncthreads();
+        for (int i = tid; i < nc; i += kT) {
+          const int X = i >> 4, r_ = i & 15;
+          double s = 0.0;
+          for (int Y = 0; Y < NT; ++Y) s += part[(X * NT + Y) * 16 + r_];
+          y[i] = s;
+        }
       }
       coarse_calls++;
       __syncthreads();
@@ -350,7 +383,8 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s) {
   const Xfer& X = d.X[ks];
   if (V.tz || V.nz != 1 || V.nx > 2 * kBW || V.ny > 2 * kBH) return hipErrorNotSupported;
   const int nc = X.cnx * X.cny;
-  if (nc > kT || nc % 2) return hipErrorNotSupported;  // the coarsest product reads output pairs
+  // the coarsest product needs the tiled lower triangle, at most 16 x 16 tiles
+  if (nc > kT || !d.Asym || d.ntile > 16 || d.ntile * 16 < nc) return hipErrorNotSupported;
   auto foot = [&](int f) { return f == 1 ? 1 : X.interp == 1 ? f : f + 2 * (f / 2) + 2; };
   if (foot(X.sx) > kFoot2 || foot(X.sy) > kFoot2) return hipErrorNotSupported;
   Small2x2Args a{};
@@ -359,7 +393,8 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s) {
   a.interp = X.interp; a.m = d.m; a.max_inner = d.max_inner;
   a.tol = d.tol[ks]; a.rel_floor2 = d.rel_floor2;
   a.tx = V.tx; a.ty = V.ty; a.rhs = d.r[ks]; a.x = d.x[ks];
-  a.Ainv = d.Ainv;
+  a.Asym = d.Asym;
+  a.ntile = d.ntile;
   a.iters = d.iters; a.calls = d.calls; a.level = ks; a.status = d.status;
   a.gate = d.gate;
   size_t off = 0;
@@ -369,8 +404,10 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s) {
     return o;
   };
   a.off_ex = take((size_t)4 * kEA * sizeof(R));
-  // the residual array also holds the coarsest partials (2 kT doubles)
-  a.off_res = take(std::max((size_t)2 * kBH * kRP * sizeof(R), (size_t)2 * kT * sizeof(double)));
+  // the residual array also holds the coarsest partials (2 kT doubles, or
+  // ntile^2 slots of 16 for the tiled product)
+  a.off_res = take(std::max({(size_t)2 * kBH * kRP * sizeof(R), (size_t)2 * kT * sizeof(double),
+                             (size_t)a.ntile * a.ntile * 16 * sizeof(double)}));
   a.off_xs = take((size_t)4 * kT * sizeof(R));
   a.off_ps = take((size_t)4 * kT * sizeof(R));
   a.off_tx1 = take((size_t)V.ny * X.cnx * sizeof(R));
