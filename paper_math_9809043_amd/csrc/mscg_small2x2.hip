@@ -40,7 +40,7 @@ constexpr int kT = 1024;               // threads
 constexpr int kBW = 32, kBH = 32;      // blocks per block row, block rows
 constexpr int kEP = kBW + 2;           // exchange array pitch (zero border)
 constexpr int kEA = (kBH + 2) * kEP;   // entries per exchange array
-constexpr int kRP = 2 * kBW;           // residual array pitch
+constexpr int kRP = 2 * kBW + 1;       // residual array pitch (odd: a column read is conflict-free)
 constexpr int kFoot2 = 12;             // >= footprint of one coarse cell along an axis (linear, s <= 4)
 
 struct Small2x2Args {
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
   __shared__ __align__(16) double sm[2][kT / kWave];
   R* ex = reinterpret_cast<R*>(lds + a.off_ex);     // [u][bq + 1][bp + 1]
   R* res = reinterpret_cast<R*>(lds + a.off_res);   // [j][i], pitch kRP
-  R* tx1 = reinterpret_cast<R*>(lds + a.off_tx1);
+  R* tx1 = reinterpret_cast<R*>(lds + a.off_tx1);  // x-pass sums, [I][row], pitch ny + 1
   double* g = reinterpret_cast<double*>(lds + a.off_g);
   double* y = reinterpret_cast<double*>(lds + a.off_y);
   double* part = reinterpret_cast<double*>(lds + a.off_res);  // coarsest partials, after the restriction
@@ -216,9 +216,12 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
       for (int u = 0; u < 4; ++u)
         if (ok[u]) res[(2 * bq + (u >> 1)) * kRP + 2 * bp + (u & 1)] = r[u] - (dg[u] * z[u] - offsum(z, u));
       __syncthreads();
-      // -- g = E^T res: x pass over (fine row, I), y pass over (J, I)
+      // -- g = E^T res: x pass over (I, fine row), rows along the lanes, then
+      // y pass over (J, I), I along the lanes; odd pitches keep both passes'
+      // LDS reads free of bank conflicts
+      const int p1 = ny + 1;
       for (int e = tid; e < ny * ncx; e += kT) {
-        const int row = e / ncx, I = e - row * ncx;
+        const int I = e / ny, row = e - I * ny;
         int lo, hi;
         ext_support(I, a.sx, nx, a.interp, lo, hi);
         R s = R(0);
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
           const int i = min(lo + b, hi);
           s += wx[I * kFoot2 + b] * res[row * kRP + i];
         }
-        tx1[e] = s;
+        tx1[I * p1 + row] = s;
       }
       __syncthreads();
       for (int e = tid; e < nc; e += kT) {
@@ -238,7 +241,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
 #pragma unroll
         for (int b = 0; b < kFoot2; ++b) {
           const int j = min(lo + b, hi);
-          s += wy[J * kFoot2 + b] * tx1[j * ncx + I];
+          s += wy[J * kFoot2 + b] * tx1[I * p1 + j];
         }
         g[e] = (double)s;
       }
@@ -410,7 +413,7 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s) {
                              (size_t)a.ntile * a.ntile * 16 * sizeof(double)}));
   a.off_xs = take((size_t)4 * kT * sizeof(R));
   a.off_ps = take((size_t)4 * kT * sizeof(R));
-  a.off_tx1 = take((size_t)V.ny * X.cnx * sizeof(R));
+  a.off_tx1 = take((size_t)(V.ny + 1) * X.cnx * sizeof(R));
   a.off_g = take((size_t)nc * sizeof(double));
   a.off_y = take((size_t)nc * sizeof(double));
   a.off_wx = take((size_t)X.cnx * kFoot2 * sizeof(R));
