@@ -30,6 +30,15 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// DPP move of a double for a pattern in which every lane has a source lane
+// (mirrors, quad permutations, row broadcasts): no old value to set up.
+template <int CTRL>
+__device__ __forceinline__ double dpp_full(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the wave, exact order fixed by the lane pattern; valid in lane 63.
 __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_d<0x111, 0xf>(v);  // row_shr:1

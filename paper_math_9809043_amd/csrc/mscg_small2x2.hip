@@ -273,18 +273,33 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
           double acc_c = 0.0;
           auto xchg = [](bool hi, double lo_v, double hi_v, auto ctrl) {
             constexpr int C = decltype(ctrl)::value;
-            return (hi ? hi_v : lo_v) + dpp_d<C, 0xf>(hi ? lo_v : hi_v);
+            return (hi ? hi_v : lo_v) + dpp_full<C>(hi ? lo_v : hi_v);
           };
+          // rows of quad q: q, q + 8, q + 4, q + 12; the next quad's loads are
+          // issued before this quad's arithmetic, so one round trip overlaps
+          // the work of the previous quad
+          struct Q4 { double a0, a1, a2, a3; };
+          auto load4 = [&](int q) {
+            Q4 v;
+            v.a0 = T[q * 16 + c];
+            v.a1 = T[(q + 8) * 16 + c];
+            v.a2 = T[(q + 4) * 16 + c];
+            v.a3 = T[(q + 12) * 16 + c];
+            return v;
+          };
+          Q4 cur = load4(0), nxt;
           auto quad = [&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            const double a0 = T[q * 16 + c], a1 = T[(q + 8) * 16 + c];
-            const double a2 = T[(q + 4) * 16 + c], a3 = T[(q + 12) * 16 + c];
-            acc_c += a0 * dpp_d<0x150 + q, 0xf>(gIc);  // row_newbcast: lane r of the row
-            acc_c += a1 * dpp_d<0x150 + q + 8, 0xf>(gIc);
-            acc_c += a2 * dpp_d<0x150 + q + 4, 0xf>(gIc);
-            acc_c += a3 * dpp_d<0x150 + q + 12, 0xf>(gIc);
+            if (q < 3) nxt = load4(q + 1);
+            asm volatile("" ::: "memory");
+            const double a0 = cur.a0, a1 = cur.a1, a2 = cur.a2, a3 = cur.a3;
+            acc_c += a0 * dpp_full<0x150 + q>(gIc);  // row_newbcast: lane r of the row
+            acc_c += a1 * dpp_full<0x150 + q + 8>(gIc);
+            acc_c += a2 * dpp_full<0x150 + q + 4>(gIc);
+            acc_c += a3 * dpp_full<0x150 + q + 12>(gIc);
             const double s0 = xchg(h8, a0 * gJc, a1 * gJc, std::integral_constant<int, 0x140>{});
             const double s1 = xchg(h8, a2 * gJc, a3 * gJc, std::integral_constant<int, 0x140>{});
+            cur = nxt;
             return xchg(h4, s0, s1, std::integral_constant<int, 0x141>{});
           };
           const double v0 = quad(std::integral_constant<int, 0>{});
