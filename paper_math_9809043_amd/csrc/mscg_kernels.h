@@ -82,8 +82,9 @@ hipError_t launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
 hipError_t launch_coarse_factor(const Lv<double>& L, double* A, double* Lrows, double* Ainv, int* status,
                                 hipStream_t s);
 hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s, const int* gate = nullptr);
-// Tile t = I (I + 1) / 2 + J (I >= J) of out holds A^-1[16 I + r][16 J + c] at
-// t 256 + 16 r + c, zero past n; ntile = ceil(n / 16) tiles per side.
+// Tile t = I (I + 1) / 2 + J (I >= J) of out holds A^-1[16 I + (s xor c)][16 J + c]
+// at t 256 + 16 s + c (skewed: slot s of column c is row s xor c), zero past n;
+// ntile = ceil(n / 16) tiles per side.
 hipError_t launch_pack_sym(const double* Ainv, int n, int ntile, double* out, hipStream_t s);
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
 hipError_t launch_init_x(double* x, int n, int nx, double hx, double Lx, double p0, double p1, int ramp, hipStream_t s);

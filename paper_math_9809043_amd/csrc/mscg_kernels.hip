@@ -1109,11 +1109,11 @@ __global__ void __launch_bounds__(256) k_band_inverse_lds(const double* __restri
 __global__ void k_pack_sym(const double* __restrict__ Ainv, int n, int NT, double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NT * (NT + 1) / 2 * 256) return;
-  const int t = e >> 8, r = (e >> 4) & 15, c = e & 15;
+  const int t = e >> 8, sl = (e >> 4) & 15, c = e & 15;
   int I = 0;
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   const int J = t - I * (I + 1) / 2;
-  const int i = 16 * I + r, j = 16 * J + c;
+  const int i = 16 * I + (sl ^ c), j = 16 * J + c;  // slot sl of column c holds row sl xor c
   out[e] = i < n && j < n ? Ainv[(long long)i * n + j] : 0.0;
 }
 

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
   R* ex = reinterpret_cast<R*>(lds + a.off_ex);     // [u][bq + 1][bp + 1]
   R* res = reinterpret_cast<R*>(lds + a.off_res);   // [j][i], pitch kRP
   R* tx1 = reinterpret_cast<R*>(lds + a.off_tx1);  // x-pass sums, [I][row], pitch ny + 1
-  double* g = reinterpret_cast<double*>(lds + a.off_g);
+  double* g = reinterpret_cast<double*>(lds + a.off_g);  // padded with zeros to 16 ntile
   double* y = reinterpret_cast<double*>(lds + a.off_y);
   double* part = reinterpret_cast<double*>(lds + a.off_res);  // coarsest partials, after the restriction
   R* xs = reinterpret_cast<R*>(lds + a.off_xs);    // iterate x, [u][tid]
@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
 
   // ---- set-up: zero the exchange arrays (their border stays zero), tables
   for (int e = tid; e < 4 * kEA; e += kT) ex[e] = R(0);
+  for (int e = nc + tid; e < 16 * a.ntile; e += kT) g[e] = 0.0;
   for (int i = tid; i < nx; i += kT) {
     int I0, I1;
     R w0, w1;
@@ -256,7 +257,7 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
         // column (slot = the other tile index), summed in slot order.
         const int NT = a.ntile, ntiles = NT * (NT + 1) / 2;
         const int grp = tid >> 4, c = tid & 15;
-        auto gat = [&](int e) { return e < nc ? g[e] : 0.0; };
+        auto gat = [&](int e) { return g[e]; };
         for (int t = grp; t < ntiles; t += kT / 16) {
           int I = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
           while (I * (I + 1) / 2 > t) --I;
@@ -264,52 +265,49 @@ __global__ void __launch_bounds__(kT, 1) k_small_2x2(Small2x2Args a) {
           const int J = t - I * (I + 1) / 2;
           const double* T = a.Asym + (long long)t * 256;
           const double gJc = gat(16 * J + c);
-          // Rows arrive in quads (q, q + 8, q + 4, q + 12): the first two
-          // exchange stages (partners 15 - c, then 7 - (c mod 8) within the
-          // half row) run as they arrive, the third (3 - (c mod 4)) once
-          // quads q and q + 2 are in, so few partial rows are ever live.
-          const bool h8 = (c & 8) != 0, h4 = (c & 4) != 0, h2 = (c & 2) != 0, h1 = (c & 1) != 0;
-          const double gIc = gat(16 * I + c);  // lane k of the group hands g_I[k] to the others
+          // The tile is stored skewed: slot s of lane c holds row s xor c
+          // (column c).  Each exchange stage then pairs slot s with slot
+          // s xor m, m = 15, 7, 3, 1 for the mirror, half-row mirror and the
+          // two quad permutations: the partner lane's slot holds the same row,
+          // so no lane has to choose what to keep or send.  Slots arrive in
+          // quads that close one second-stage value each.
+          const double* Tl = T + c;
           double acc_c = 0.0;
-          auto xchg = [](bool hi, double lo_v, double hi_v, auto ctrl) {
-            constexpr int C = decltype(ctrl)::value;
-            return (hi ? hi_v : lo_v) + dpp_full<C>(hi ? lo_v : hi_v);
+          auto quad = [&](auto s0c, const double (&v)[4]) {
+            constexpr int s0 = decltype(s0c)::value;  // slots s0, s0 ^ 15, s0 ^ 7, s0 ^ 8
+            constexpr int sl[4] = {s0, s0 ^ 15, s0 ^ 7, s0 ^ 8};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc_c += v[k] * gat(16 * I + (sl[k] ^ c));
+            const double u_a = v[0] * gJc + dpp_full<0x140>(v[1] * gJc);  // slot s0 (mirror)
+            const double u_b = v[2] * gJc + dpp_full<0x140>(v[3] * gJc);  // slot s0 ^ 7
+            return u_a + dpp_full<0x141>(u_b);                            // half-row mirror
           };
-          // rows of quad q: q, q + 8, q + 4, q + 12; the next quad's loads are
-          // issued before this quad's arithmetic, so one round trip overlaps
-          // the work of the previous quad
-          struct Q4 { double a0, a1, a2, a3; };
-          auto load4 = [&](int q) {
-            Q4 v;
-            v.a0 = T[q * 16 + c];
-            v.a1 = T[(q + 8) * 16 + c];
-            v.a2 = T[(q + 4) * 16 + c];
-            v.a3 = T[(q + 12) * 16 + c];
-            return v;
+          auto load = [&](int s0, double (&v)[4]) {
+            v[0] = Tl[s0 * 16];
+            v[1] = Tl[(s0 ^ 15) * 16];
+            v[2] = Tl[(s0 ^ 7) * 16];
+            v[3] = Tl[(s0 ^ 8) * 16];
           };
-          Q4 cur = load4(0), nxt;
-          auto quad = [&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if (q < 3) nxt = load4(q + 1);
-            asm volatile("" ::: "memory");
-            const double a0 = cur.a0, a1 = cur.a1, a2 = cur.a2, a3 = cur.a3;
-            acc_c += a0 * dpp_full<0x150 + q>(gIc);  // row_newbcast: lane r of the row
-            acc_c += a1 * dpp_full<0x150 + q + 8>(gIc);
-            acc_c += a2 * dpp_full<0x150 + q + 4>(gIc);
-            acc_c += a3 * dpp_full<0x150 + q + 12>(gIc);
-            const double s0 = xchg(h8, a0 * gJc, a1 * gJc, std::integral_constant<int, 0x140>{});
-            const double s1 = xchg(h8, a2 * gJc, a3 * gJc, std::integral_constant<int, 0x140>{});
-            cur = nxt;
-            return xchg(h4, s0, s1, std::integral_constant<int, 0x141>{});
-          };
-          const double v0 = quad(std::integral_constant<int, 0>{});
-          const double v1 = quad(std::integral_constant<int, 1>{});
-          const double w0 = xchg(h2, v0, quad(std::integral_constant<int, 2>{}), std::integral_constant<int, 0x1B>{});
-          const double w1 = xchg(h2, v1, quad(std::integral_constant<int, 3>{}), std::integral_constant<int, 0x1B>{});
+          // quads for the second-stage slots 0, 3 (-> third-stage slot 0) and 1, 2 (-> 1);
+          // the next quad's loads go out before this quad's arithmetic
+          double qa[4], qb[4];
+          load(0, qa);
+          load(3, qb);
+          asm volatile("" ::: "memory");
+          const double w0 = quad(std::integral_constant<int, 0>{}, qa);
+          load(1, qa);
+          asm volatile("" ::: "memory");
+          const double w3 = quad(std::integral_constant<int, 3>{}, qb);
+          load(2, qb);
+          asm volatile("" ::: "memory");
+          const double v0 = w0 + dpp_full<0x1B>(w3);  // quad permutation 3 - (c mod 4)
+          const double w1 = quad(std::integral_constant<int, 1>{}, qa);
+          const double w2 = quad(std::integral_constant<int, 2>{}, qb);
+          const double v1 = w1 + dpp_full<0x1B>(w2);
           part[(J * NT + I) * 16 + c] = acc_c;
           if (I != J) {  // the same for all 16 lanes of the group
             // partner c xor 1: lane c ends with the total of row c
-            const double row = xchg(h1, w0, w1, std::integral_constant<int, 0xB1>{});
+            const double row = v0 + dpp_full<0xB1>(v1);
             part[(I * NT + J) * 16 + c] = row;
           }
         }
@@ -429,7 +427,7 @@ hipError_t launch_small_2x2(const SmallDesc<R>& d, hipStream_t s) {
   a.off_xs = take((size_t)4 * kT * sizeof(R));
   a.off_ps = take((size_t)4 * kT * sizeof(R));
   a.off_tx1 = take((size_t)(V.ny + 1) * X.cnx * sizeof(R));
-  a.off_g = take((size_t)nc * sizeof(double));
+  a.off_g = take((size_t)16 * d.ntile * sizeof(double));
   a.off_y = take((size_t)nc * sizeof(double));
   a.off_wx = take((size_t)X.cnx * kFoot2 * sizeof(R));
   a.off_wy = take((size_t)X.cny * kFoot2 * sizeof(R));
