@@ -28,7 +28,7 @@ namespace {
 constexpr int kHalo = 9;  // 2m + 1 for m = 4
 
 template <typename R, bool POST, int TW, int TH, int BX, int BY>
-__global__ void __launch_bounds__(BX* BY) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
+__global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4 : 1) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                          const R* __restrict__ zin, const R* __restrict__ y,
                                                          R* __restrict__ zout, const int* __restrict__ gate,
                                                          double* __restrict__ part) {
