@@ -198,6 +198,7 @@ struct mscg_problem {
   int tile_shape;     // its tile shape (-1: by level size)
   bool fuse_dot;      // the tiled post-smoother also forms the CG's r . z
   bool sym_coarse;    // one-workgroup solvers apply the coarsest inverse from its lower triangle
+  bool fuse_finish;   // the SpMV and update kernels sum the r.z and p.q partials themselves
   int small_variant;  // one-workgroup kernel of 2-D small levels (0 2x2-block, else colour-split; 1 cell-strided; 2 colour-split)
   // per-solve state
   double eps2;
@@ -391,7 +392,7 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
     double* fpart = nullptr;
     if (nfused && P->fuse_dot && !P->o.flexible) {
       const int nt = smooth_tile_count(L.nx, L.ny, P->tile_shape);
-      if (nt <= kPartSlots) {
+      if (nt <= kPartPq) {
         fpart = P->part;
         *nfused = nt;
       }
@@ -453,8 +454,10 @@ int apply_prec(mscg_problem* P, int k, void** out, const int* gate, int* nfused 
 // One level's CG loop (Templates Figure 2.5) on vectors of type R; the residual
 // is in r_k and the entry check has been done (sc->converged).  Per iteration:
 // the preconditioner, r.z, p and A p with p.q, then the x / r update with
-// |r|^2, each reduction followed by its one-workgroup finish (r.z comes as
-// per-tile partials from the tiled post-smoother where that runs).  The directions
+// |r|^2.  r.z comes as per-tile partials from the tiled post-smoother where
+// that runs; the SpMV kernel sums them itself (beta) and the update kernel
+// sums them and the p.q partials (alpha), so only |r|^2 has a one-workgroup
+// finish (with the flexible beta, every reduction has one).  The directions
 // alternate between p and p2 (the next one is formed from the current one on
 // the fly, inside the SpMV).
 //
@@ -482,14 +485,26 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p
       rc = apply_prec(P, k, &zres, gate, &nfused);
       if (rc) return rc;
       z = static_cast<R*>(zres);
-      if (P->o.flexible && queued > 0)
-        HIP_TRY(launch_dot_fin<R>(z, q, L.n, P->part, nb, H.sc, kOpZq, P->stream, gate));
-      if (nfused)
-        HIP_TRY(launch_finish(P->part, nfused, H.sc, kOpRho, P->stream, gate));
-      else
-        HIP_TRY(launch_dot_fin<R>(r, z, L.n, P->part, nb, H.sc, kOpRho, P->stream, gate));
-      HIP_TRY(launch_pspmv_fin<R>(L, z, pc, pn, q, P->part, nb, H.sc, P->stream, gate));
-      HIP_TRY(launch_cg_update_fin<R>(x, r, pn, q, L.n, P->part, nb, H.sc, P->stream, gate));
+      if (P->fuse_finish && !P->o.flexible) {
+        // r.z and p.q summed by the kernels that need them (no finish kernels)
+        int nrho = nfused;
+        if (!nrho) {
+          HIP_TRY(launch_dot_part<R>(r, z, L.n, P->part, nb, P->stream, gate));
+          nrho = nb;
+        }
+        HIP_TRY(launch_pspmv_rho<R>(L, z, pc, pn, q, P->part, nrho, P->part + kPartPq, nb, H.sc, P->stream, gate));
+        HIP_TRY(launch_update_pq_fin<R>(x, r, pn, q, L.n, P->part, nrho, P->part + kPartPq, P->part + kPartRr, nb,
+                                        H.sc, P->stream, gate));
+      } else {
+        if (P->o.flexible && queued > 0)
+          HIP_TRY(launch_dot_fin<R>(z, q, L.n, P->part, nb, H.sc, kOpZq, P->stream, gate));
+        if (nfused)
+          HIP_TRY(launch_finish(P->part, nfused, H.sc, kOpRho, P->stream, gate));
+        else
+          HIP_TRY(launch_dot_fin<R>(r, z, L.n, P->part, nb, H.sc, kOpRho, P->stream, gate));
+        HIP_TRY(launch_pspmv_fin<R>(L, z, pc, pn, q, P->part, nb, H.sc, P->stream, gate));
+        HIP_TRY(launch_cg_update_fin<R>(x, r, pn, q, L.n, P->part, nb, H.sc, P->stream, gate));
+      }
       std::swap(pc, pn);
     }
     rc = read_scal(P, k);
@@ -702,6 +717,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
     P->tiled = !(e && e[0] == '1');
     const char* fd = getenv("MSCG_FUSED_DOT");
     P->fuse_dot = !(fd && fd[0] == '0');
+    const char* ff = getenv("MSCG_FUSED_FINISH");
+    P->fuse_finish = !(ff && ff[0] == '0');
     const char* sy = getenv("MSCG_SYM_COARSE");
     P->sym_coarse = !(sy && sy[0] == '0');
     const char* t = getenv("MSCG_TILE_SHAPE");

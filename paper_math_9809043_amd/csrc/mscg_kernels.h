@@ -10,6 +10,8 @@ namespace mscg {
 
 constexpr int kMaxPartials = 1024;  // blocks of a grid-wide reduction
 constexpr int kPartSlots = 8192;    // partials the workspace holds (the tiled post-smoother's r . z per tile)
+constexpr int kPartPq = 4096;       // offsets of the p.q and |r|^2 partials when the finishes are folded in
+constexpr int kPartRr = 6144;
 
 // Device-resident scalars of one level's CG (Templates Figure 2.5).
 struct Scal {
@@ -136,6 +138,23 @@ hipError_t launch_pspmv_fin(const Lv<R>& L, const R* z, const R* pold, R* pnew, 
 template <typename R>
 hipError_t launch_cg_update_fin(R* x, R* r, const R* p, const R* q, int n, double* part, int nparts, Scal* sc,
                                 hipStream_t s, const int* gate = nullptr);
+// The CG iteration with the r.z and p.q finishes folded into the kernels that
+// consume them: launch_dot_part leaves r.z partials (no finish);
+// launch_pspmv_rho sums them in every workgroup (beta), forms p and q = A p
+// and leaves p.q partials in ppq; launch_update_pq_fin sums both (alpha),
+// updates x and r, leaves |r|^2 partials in prr and runs their finish.  The
+// three partial arrays must not overlap.  Bitwise the same as the finished
+// path (same sums in the same order).
+template <typename R>
+hipError_t launch_dot_part(const R* a, const R* b, int n, double* part, int nparts, hipStream_t s,
+                           const int* gate = nullptr);
+template <typename R>
+hipError_t launch_pspmv_rho(const Lv<R>& L, const R* z, const R* pold, R* pnew, R* q, const double* prho, int nrho,
+                            double* ppq, int nparts, Scal* sc, hipStream_t s, const int* gate = nullptr);
+template <typename R>
+hipError_t launch_update_pq_fin(R* x, R* r, const R* p, const R* q, int n, const double* prho, int nrho,
+                                const double* ppq, double* prr, int nparts, Scal* sc, hipStream_t s,
+                                const int* gate = nullptr);
 template <typename R>
 hipError_t launch_fill(R* a, long long n, R v, hipStream_t s);
 template <typename R>

@@ -654,28 +654,38 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return block_sum(acc, sm);
 }
 
-__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
-                                                   int op, const int* __restrict__ gate) {
-  // the gate, the scalars and (up to 8 per thread) the partials are read in
-  // one round trip; the sum keeps the order of sum_partials
-  const int gv = *gate_or_zero(gate);
-  Scal loc = *sc;
-  constexpr int kF = 8;
-  double pv[kF];
+// Partials read in one batch (up to kPF per thread, issued together with
+// whatever else the kernel needs first), then summed in the order of
+// sum_partials: every workgroup that sums the same partials gets the same bits.
+constexpr int kPF = 8;
+__device__ __forceinline__ void load_partials(const double* __restrict__ part, int nparts, double (&pv)[kPF]) {
 #pragma unroll
-  for (int u = 0; u < kF; ++u) {
+  for (int u = 0; u < kPF; ++u) {
     const int q = threadIdx.x + u * blockDim.x;
     pv[u] = q < nparts ? part[q] : 0.0;
   }
+}
+__device__ __forceinline__ double sum_loaded_partials(const double (&pv)[kPF], const double* __restrict__ part,
+                                                      int nparts, double* sm) {
+  double acc = pv[0];
+#pragma unroll
+  for (int u = 1; u < kPF; ++u) acc += pv[u];
+  for (int q = threadIdx.x + kPF * blockDim.x; q < nparts; q += blockDim.x) acc += part[q];
+  return block_sum(acc, sm);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int nparts, Scal* __restrict__ sc,
+                                                   int op, const int* __restrict__ gate) {
+  // the gate, the scalars and the partials are read in one round trip
+  const int gv = *gate_or_zero(gate);
+  Scal loc = *sc;
+  double pv[kPF];
+  load_partials(part, nparts, pv);
   issue_before(gv);
   issue_before(loc.rho);
   if (gv) return;
-  double acc = pv[0];
-#pragma unroll
-  for (int u = 1; u < kF; ++u) acc += pv[u];
-  for (int q = threadIdx.x + kF * blockDim.x; q < nparts; q += blockDim.x) acc += part[q];
   __shared__ double sm[kBlock / kWave];
-  const double s = block_sum(acc, sm);
+  const double s = sum_loaded_partials(pv, part, nparts, sm);
   if (threadIdx.x == 0) {
     apply_op(s, &loc, op);
     *sc = loc;
@@ -695,23 +705,12 @@ __global__ void __launch_bounds__(kBlock) k_dot_g(const R* __restrict__ a, const
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// p_new = z (first iteration) or z + beta p_old, q = A p_new with partial
-// sums of p.q; the neighbours' p_new are formed from z and p_old on the fly
-// (p_new and p_old are different buffers).
+// p_new = z (first iteration) or z + beta p_old, q = A p_new over this
+// thread's cells; returns its part of p_new . q.  The neighbours' p_new are
+// formed from z and p_old on the fly (p_new and p_old are different buffers).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_pspmv(Lv<R> L, const R* __restrict__ z, const R* __restrict__ pold,
-                                                   R* __restrict__ pnew, R* __restrict__ q, double* __restrict__ part,
-                                                   const Scal* __restrict__ sc, const int* __restrict__ gate) {
-  const int gv = *gate_or_zero(gate);
-  const int it = sc->it;
-  const double beta_d = sc->beta;
-  issue_before(gv);
-  issue_before(it);
-  issue_before(beta_d);
-  if (gv) return;
-  __shared__ double sm[kBlock / kWave];
-  const bool first = it == 0;
-  const R beta = (R)beta_d;
+__device__ __forceinline__ double pspmv_range(const Lv<R>& L, const R* __restrict__ z, const R* __restrict__ pold,
+                                              R* __restrict__ pnew, R* __restrict__ q, bool first, R beta) {
   auto pv = [&](int c) { return first ? z[c] : z[c] + beta * pold[c]; };
   double acc = 0.0;
   const int nx = L.nx, ny = L.ny;
@@ -741,8 +740,62 @@ __global__ void __launch_bounds__(kBlock) k_pspmv(Lv<R> L, const R* __restrict__
     q[c] = v;
     acc += (double)pc * (double)v;
   }
+  return acc;
+}
+
+// The direction update and SpMV with partial sums of p.q (beta from sc).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pspmv(Lv<R> L, const R* __restrict__ z, const R* __restrict__ pold,
+                                                   R* __restrict__ pnew, R* __restrict__ q, double* __restrict__ part,
+                                                   const Scal* __restrict__ sc, const int* __restrict__ gate) {
+  const int gv = *gate_or_zero(gate);
+  const int it = sc->it;
+  const double beta_d = sc->beta;
+  issue_before(gv);
+  issue_before(it);
+  issue_before(beta_d);
+  if (gv) return;
+  __shared__ double sm[kBlock / kWave];
+  const double acc = pspmv_range(L, z, pold, pnew, q, it == 0, (R)beta_d);
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// The same with the finish of r.z folded in: every workgroup sums the r.z
+// partials itself (same order as k_finish, so the same rho and beta), and
+// workgroup 0 does the bookkeeping of that finish once.  rho itself is stored
+// by the update kernel that follows: the workgroups here still read the
+// previous one.  On a breakdown every workgroup stops before writing.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pspmv_rho(Lv<R> L, const R* __restrict__ z, const R* __restrict__ pold,
+                                                       R* __restrict__ pnew, R* __restrict__ q,
+                                                       const double* __restrict__ prho, int nrho,
+                                                       double* __restrict__ ppq, Scal* __restrict__ sc,
+                                                       const int* __restrict__ gate) {
+  const int gv = *gate_or_zero(gate);
+  const int it = sc->it;
+  const double rho_prev = sc->rho;
+  double pv[kPF];
+  load_partials(prho, nrho, pv);
+  issue_before(gv);
+  issue_before(it);
+  issue_before(rho_prev);
+  if (gv) return;
+  __shared__ double sm[kBlock / kWave];
+  const double s = sum_loaded_partials(pv, prho, nrho, sm);
+  const bool nonfinite = !(s == s) || s == INFINITY;
+  const bool stop = nonfinite || !(s > 0.0);
+  const double beta_d = it == 0 ? 0.0 : s / rho_prev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->started += 1;
+    if (nonfinite) { sc->status = -4; sc->converged = 1; }
+    else if (stop) { sc->status = 1; sc->converged = 1; }
+    sc->beta = beta_d;
+  }
+  if (stop) return;
+  const double acc = pspmv_range(L, z, pold, pnew, q, it == 0, (R)beta_d);
+  const double t = block_sum(acc, sm);
+  if (threadIdx.x == 0) ppq[blockIdx.x] = t;
 }
 
 // x += alpha p, r -= alpha q with partial sums of |r|^2 (gated)
@@ -767,6 +820,50 @@ __global__ void __launch_bounds__(kBlock) k_cg_update_g(R* __restrict__ x, R* __
   }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q with partial sums of |r|^2, the finish of p.q
+// folded in: every workgroup sums the r.z and p.q partials itself (same order
+// as k_finish, so the same alpha = rho / p.q), workgroup 0 stores rho, alpha
+// and the breakdown state once.  On a breakdown every workgroup stops before
+// writing.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_update_pq(R* __restrict__ x, R* __restrict__ r, const R* __restrict__ p,
+                                                       const R* __restrict__ q, int n, const double* __restrict__ prho,
+                                                       int nrho, const double* __restrict__ ppq, int npq,
+                                                       double* __restrict__ prr, Scal* __restrict__ sc,
+                                                       const int* __restrict__ gate) {
+  const int gv = *gate_or_zero(gate);
+  const int status = sc->status;
+  double pr[kPF], pp[kPF];
+  load_partials(prho, nrho, pr);
+  load_partials(ppq, npq, pp);
+  issue_before(gv);
+  issue_before(status);
+  if (gv) return;
+  __shared__ double sm[kBlock / kWave];
+  const double rho = sum_loaded_partials(pr, prho, nrho, sm);
+  const double pq = sum_loaded_partials(pp, ppq, npq, sm);
+  const bool nonfinite = !(pq == pq) || pq == INFINITY;
+  const bool stop = nonfinite || !(pq > 0.0) || status != 0;
+  const double alpha_d = stop ? 0.0 : rho / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rho = rho;
+    sc->alpha = alpha_d;
+    if (nonfinite) { sc->status = -4; sc->converged = 1; }
+    else if (stop) { if (status == 0) sc->status = 1; sc->converged = 1; }
+  }
+  if (stop) return;
+  const R alpha = (R)alpha_d;
+  double acc = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    x[c] += alpha * p[c];
+    const R v = r[c] - alpha * q[c];
+    r[c] = v;
+    acc += (double)v * (double)v;
+  }
+  const double t = block_sum(acc, sm);
+  if (threadIdx.x == 0) prr[blockIdx.x] = t;
 }
 
 __global__ void k_rhs(RhsArgs a) {
@@ -1269,6 +1366,30 @@ hipError_t launch_cg_update_fin(R* x, R* r, const R* p, const R* q, int n, doubl
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_dot_part(const R* a, const R* b, int n, double* part, int nparts, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_dot_g<R>, dim3(nparts), dim3(kBlock), 0, s, a, b, n, part, gate);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pspmv_rho(const Lv<R>& L, const R* z, const R* pold, R* pnew, R* q, const double* prho, int nrho,
+                            double* ppq, int nparts, Scal* sc, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_pspmv_rho<R>, dim3(nparts), dim3(kBlock), 0, s, L, z, pold, pnew, q, prho, nrho, ppq, sc,
+                     gate);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_update_pq_fin(R* x, R* r, const R* p, const R* q, int n, const double* prho, int nrho,
+                                const double* ppq, double* prr, int nparts, Scal* sc, hipStream_t s,
+                                const int* gate) {
+  hipLaunchKernelGGL(k_update_pq<R>, dim3(nparts), dim3(kBlock), 0, s, x, r, p, q, n, prho, nrho, ppq, nparts, prr,
+                     sc, gate);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, (const double*)prr, nparts, sc, (int)kOpRr, gate);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish(const double* part, int nparts, Scal* sc, int op, hipStream_t s, const int* gate) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, nparts, sc, op, gate);
   return hipGetLastError();
@@ -1383,6 +1504,11 @@ hipError_t launch_small_pcg(const SmallDesc<R>& d, hipStream_t s) {
                                           hipStream_t, const int*);                                                \
   template hipError_t launch_cg_update_fin<R>(R*, R*, const R*, const R*, int, double*, int, Scal*, hipStream_t, \
                                               const int*);                                                         \
+  template hipError_t launch_dot_part<R>(const R*, const R*, int, double*, int, hipStream_t, const int*);       \
+  template hipError_t launch_pspmv_rho<R>(const Lv<R>&, const R*, const R*, R*, R*, const double*, int, double*, \
+                                          int, Scal*, hipStream_t, const int*);                                    \
+  template hipError_t launch_update_pq_fin<R>(R*, R*, const R*, const R*, int, const double*, int, const double*, \
+                                              double*, int, Scal*, hipStream_t, const int*);                      \
   template hipError_t launch_fill<R>(R*, long long, R, hipStream_t);                                              \
   template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);                                       \
   template hipError_t launch_small_pcg<R>(const SmallDesc<R>&, hipStream_t);

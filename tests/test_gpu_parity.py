@@ -306,6 +306,28 @@ def test_fused_rho_matches_grid_wide_dot(name, make, opt, monkeypatch):
 
 
 @pytest.mark.parametrize("name,make,opt", [
+    ("smooth512", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {}),
+    ("smooth512_mixed", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {"precision": 1}),
+    ("layered32_semi", lambda: synth.layered_3d(2, 32, n_layers=4),
+     {"interp": 1, "semi_coarsen": 1, "axis_weight": (1, 1, 0.01)}),
+], ids=["smooth512", "smooth512_mixed", "layered32_semi"])
+def test_folded_finishes_match_finish_kernels_bitwise(name, make, opt, monkeypatch):
+    """r.z and p.q summed inside the SpMV and update kernels (every workgroup
+    the same partials in the same order) give the bits of the path with a
+    finish kernel after each reduction."""
+    P = make()
+    out = {}
+    for ff in ("0", "1"):
+        case(f"folded finishes {ff} {name}")
+        monkeypatch.setenv("MSCG_FUSED_FINISH", ff)
+        st, x, _ = gpu_solve(P, **opt)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        out[ff] = (st, x)
+    assert out["0"][0].level_iters == out["1"][0].level_iters
+    assert np.array_equal(out["0"][1], out["1"][1])
+
+
+@pytest.mark.parametrize("name,make,opt", [
     ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
     ("rect288x160", lambda: synth.smoothed_lognormal_2d(7, 288, 160, lo=-3, hi=3), {}),
     ("smooth256_const", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"interp": 1}),
