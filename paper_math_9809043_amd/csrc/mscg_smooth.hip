@@ -232,10 +232,12 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_resid_restrict_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                              const R* __restrict__ z, R* __restrict__ g,
                                                              const int* __restrict__ gate) {
-  if (gate && *gate) return;
+  constexpr int kZ = (kRegH + 2) * (kRegW + 2), kC = kRegH * kRegW;
+  constexpr int kZPer = (kZ + 255) / 256, kCPer = (kC + 255) / 256;
   __shared__ R zs[kRegH + 2][kRegW + 2];
   __shared__ R res[kRegH][kRegW];
   __shared__ R tmp[kRegH][kCTx];
+  __shared__ R wxt[kCTx][kFootMax], wyt[kCTy][kFootMax];  // footprint weights of the block's coarse columns, rows
   const int nx = L.nx, ny = L.ny, tid = threadIdx.x;
   const int I0 = blockIdx.x * kCTx, J0 = blockIdx.y * kCTy;
   const int I1 = min(I0 + kCTx, X.cnx) - 1, J1 = min(J0 + kCTy, X.cny) - 1;
@@ -245,49 +247,89 @@ __global__ void __launch_bounds__(256) k_resid_restrict_tile(Lv<R> L, Xfer X, co
   ext_support(J0, X.sy, ny, X.interp, loy, t0);
   ext_support(J1, X.sy, ny, X.interp, t1, hiy);
   const int RW = hix - lox + 1, RH = hiy - loy + 1;
-  // z on the region and a one-cell ring (zero outside the grid: those terms are skipped)
-  for (int e = tid; e < (RH + 2) * (RW + 2); e += blockDim.x) {
+  // every load of the block first, with the gate: one round trip to memory.
+  // z on the region and a one-cell ring (zero outside the grid: those terms
+  // are skipped); T and r of the region's cells
+  const int gv = gate ? *gate : 0;
+  R zv[kZPer];
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int e = tid + 256 * u;
     const int lj = e / (RW + 2), li = e - lj * (RW + 2);
     const int i = lox - 1 + li, j = loy - 1 + lj;
-    zs[lj][li] = (i >= 0 && i < nx && j >= 0 && j < ny) ? z[i + nx * j] : R(0);
+    zv[u] = (e < (RH + 2) * (RW + 2) && i >= 0 && i < nx && j >= 0 && j < ny) ? z[i + nx * j] : R(0);
   }
-  __syncthreads();
-  for (int e = tid; e < RH * RW; e += blockDim.x) {
-    const int lj = e / RW, li = e - lj * RW;
+  R cw[kCPer], ce[kCPer], cs[kCPer], cn[kCPer], rv[kCPer];
+#pragma unroll
+  for (int u = 0; u < kCPer; ++u) {
+    const int e = tid + 256 * u;
+    const bool in = e < RH * RW;
+    const int lj = in ? e / RW : 0, li = in ? e - lj * RW : 0;
     const int i = lox + li, j = loy + lj;
     const int fx = i + (nx + 1) * j, fy = i + nx * j;
-    const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
+    cw[u] = in ? L.tx[fx] : R(0);
+    ce[u] = in ? L.tx[fx + 1] : R(0);
+    cs[u] = in ? L.ty[fy] : R(0);
+    cn[u] = in ? L.ty[fy + nx] : R(0);
+    rv[u] = in ? r[fy] : R(0);
+  }
+  asm volatile("" ::"v"(gv));  // the gate's wait comes after every load is issued
+  if (gv) return;
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int e = tid + 256 * u;
+    if (e < (RH + 2) * (RW + 2)) zs[e / (RW + 2)][e % (RW + 2)] = zv[u];
+  }
+  if (tid < kCTx * kFootMax) {
+    const int c = tid / kFootMax, b = tid - c * kFootMax, I = I0 + c;
+    int ilo, ihi;
+    ext_support(I, X.sx, nx, X.interp, ilo, ihi);
+    wxt[c][b] = (I <= I1 && ilo + b <= ihi) ? ext_weight_of<R>(ilo + b, I, X.sx, X.cnx, X.interp) : R(0);
+  } else if (tid < kCTx * kFootMax + kCTy * kFootMax) {
+    const int t = tid - kCTx * kFootMax, c = t / kFootMax, b = t - c * kFootMax, J = J0 + c;
+    int jlo, jhi;
+    ext_support(J, X.sy, ny, X.interp, jlo, jhi);
+    wyt[c][b] = (J <= J1 && jlo + b <= jhi) ? ext_weight_of<R>(jlo + b, J, X.sy, X.cny, X.interp) : R(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kCPer; ++u) {
+    const int e = tid + 256 * u;
+    if (e >= RH * RW) continue;
+    const int lj = e / RW, li = e - lj * RW;
+    const int i = lox + li, j = loy + lj;
+    const R tw = cw[u], te = ce[u], ts = cs[u], tn = cn[u];
     const R d = tw + te + ts + tn;
     R o = R(0);
     if (i > 0) o += tw * zs[lj + 1][li];
     if (i < nx - 1) o += te * zs[lj + 1][li + 2];
     if (j > 0) o += ts * zs[lj][li + 1];
     if (j < ny - 1) o += tn * zs[lj + 2][li + 1];
-    res[lj][li] = r[fy] - (d * zs[lj + 1][li + 1] - o);
+    res[lj][li] = rv[u] - (d * zs[lj + 1][li + 1] - o);
   }
   __syncthreads();
   // x pass: row lj against the weights of coarse column I over its footprint
   for (int e = tid; e < RH * kCTx; e += blockDim.x) {
-    const int lj = e / kCTx, I = I0 + (e - lj * kCTx);
+    const int lj = e / kCTx, c = e - lj * kCTx, I = I0 + c;
     if (I > I1) continue;
     int ilo, ihi;
     ext_support(I, X.sx, nx, X.interp, ilo, ihi);
     R racc = R(0);
-    for (int i = ilo; i <= ihi; ++i) racc += ext_weight_of<R>(i, I, X.sx, X.cnx, X.interp) * res[lj][i - lox];
-    tmp[lj][e - lj * kCTx] = racc;
+    for (int i = ilo; i <= ihi; ++i) racc += wxt[c][i - ilo] * res[lj][i - lox];
+    tmp[lj][c] = racc;
   }
   __syncthreads();
   // y pass
   for (int e = tid; e < kCTy * kCTx; e += blockDim.x) {
-    const int J = J0 + e / kCTx, I = I0 + e % kCTx;
+    const int cj = e / kCTx, c = e % kCTx, J = J0 + cj, I = I0 + c;
     if (J > J1 || I > I1) continue;
     int jlo, jhi;
     ext_support(J, X.sy, ny, X.interp, jlo, jhi);
     R acc = R(0);
     for (int j = jlo; j <= jhi; ++j) {
-      const R wj = ext_weight_of<R>(j, J, X.sy, X.cny, X.interp);
+      const R wj = wyt[cj][j - jlo];
       if (wj == R(0)) continue;
-      acc += (R(1) * wj) * tmp[j - loy][e % kCTx];
+      acc += (R(1) * wj) * tmp[j - loy][c];
     }
     g[I + X.cnx * J] = acc;
   }
