@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
                                                          const R* __restrict__ zin, const R* __restrict__ y,
                                                          R* __restrict__ zout, const int* __restrict__ gate,
                                                          double* __restrict__ part) {
-  if (gate && *gate) return;
+  const int gv = gate ? *gate : 0;
   constexpr int MW = TW + 2 * kHalo, MH = TH + 2 * kHalo;
   constexpr int HW = (MW + 1) / 2;         // cells of one colour per region row, upper bound
   constexpr int NR = (MH + BY - 1) / BY;   // region rows per thread
@@ -44,83 +44,196 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
   const int RW = min(x0 + TW + kHalo, nx) - rx0, RH = min(y0 + TH + kHalo, ny) - ry0;
   const int k = threadIdx.x % BX, ty = threadIdx.x / BX;
 
-  // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
-  // within its colour.  The thread's cell of colour c in row lj is
-  // li = 2k + ((rx0 + ry0 + lj + c) & 1).
-  int xI0[2], xI1[2];
-  R xw0[2], xw1[2];
-  // post-smoothing: the coarse values the region's prolongation reads are
-  // staged in LDS when the patch fits (factors >= 2 per axis)
-  constexpr int kPW = MW / 2 + 2, kPH = MH / 2 + 2;
-  __shared__ R ys[POST ? kPW * kPH : 1];
-  int pI = 0, pJ = 0, PW = 0;
-  bool staged = false;
-  if (POST) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
-    int a0, a1, b0, b1;
-    R u0, u1;
-    ext_weights<R>(rx0, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
-    pI = a0;
-    ext_weights<R>(rx0 + RW - 1, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
-    PW = a1 - pI + 1;
-    ext_weights<R>(ry0, X.sy, X.cny, X.interp, b0, u0, b1, u1);
-    pJ = b0;
-    ext_weights<R>(ry0 + RH - 1, X.sy, X.cny, X.interp, b0, u0, b1, u1);
-    const int PH = b1 - pJ + 1;
-    staged = PW <= kPW && PH <= kPH;  // the same for every thread
-    if (staged) {
-      for (int e = threadIdx.x; e < PW * PH; e += BX * BY) {
-        const int jj = e / PW, ii = e - jj * PW;
-        ys[e] = y[(pI + ii) + X.cnx * (pJ + jj)];
-      }
-      __syncthreads();
-    }
-  }
-  auto yv = [&](int I, int J) { return staged ? ys[(J - pJ) * PW + (I - pI)] : y[I + X.cnx * J]; };
+  // Small tiles (latency-bound levels) and the pre-smoother issue every load
+  // before the first wait; the post-smoother on large tiles, which runs at
+  // its register limit, stages the coarse patch first (gate, patch, then the
+  // coefficients: three round trips, fewer live registers).
+  constexpr bool kEarly = !POST || TW * TH <= 196;
   R cw[NR][2], ce[NR][2], cs[NR][2], cn[NR][2], dg[NR][2], rr[NR][2];
+  if constexpr (kEarly) {
+    // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
+    // within its colour.  The thread's cell of colour c in row lj is
+    // li = 2k + ((rx0 + ry0 + lj + c) & 1).
+    R zp[NR][2];
 #pragma unroll
-  for (int b = 0; b < NR; ++b) {
-    const int lj = ty + BY * b;
-    const int j = ry0 + lj;
-    int J0 = 0, J1 = 0;
-    R wj0 = R(0), wj1 = R(0);
-    if (POST && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
+    for (int b = 0; b < NR; ++b) {
+      const int lj = ty + BY * b;
+      const int j = ry0 + lj;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int q = (rx0 + ry0 + lj + c) & 1;
-      const int li = 2 * k + q;
-      cw[b][c] = ce[b][c] = cs[b][c] = cn[b][c] = R(0);
-      dg[b][c] = R(1);  // inverse diagonal
-      rr[b][c] = R(0);
-      if (lj < RH && li < RW) {
-        const int i = rx0 + li;
-        const int fx = i + (nx + 1) * j, fy = i + nx * j;
-        const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
-        dg[b][c] = R(1) / (tw + te + ts + tn);
-        if (i > 0 && li > 0) cw[b][c] = tw;
-        if (i < nx - 1 && li < RW - 1) ce[b][c] = te;
-        if (j > 0 && lj > 0) cs[b][c] = ts;
-        if (j < ny - 1 && lj < RH - 1) cn[b][c] = tn;
-        rr[b][c] = r[i + nx * j];
-        if (POST) {
-          // same products, in the same order, as the grid-wide prolongation
-          R v = R(0);
-          if (wj0 != R(0)) {
-            if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * yv(xI0[q], J0);
-            if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * yv(xI1[q], J0);
-          }
-          if (wj1 != R(0)) {
-            if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * yv(xI0[q], J1);
-            if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * yv(xI1[q], J1);
-          }
-          zc[c][lj][k] = zin[i + nx * j] + v;
+      for (int c = 0; c < 2; ++c) {
+        const int li = 2 * k + ((rx0 + ry0 + lj + c) & 1);
+        cw[b][c] = ce[b][c] = cs[b][c] = cn[b][c] = rr[b][c] = zp[b][c] = R(0);
+        if (lj < RH && li < RW) {
+          const int i = rx0 + li;
+          const int fx = i + (nx + 1) * j, fy = i + nx * j;
+          cw[b][c] = L.tx[fx];
+          ce[b][c] = L.tx[fx + 1];
+          cs[b][c] = L.ty[fy];
+          cn[b][c] = L.ty[fy + nx];
+          rr[b][c] = r[i + nx * j];
+          if (POST) zp[b][c] = zin[i + nx * j];
         }
       }
     }
+    // post-smoothing: the coarse values the region's prolongation reads are
+    // staged in LDS when the patch fits (factors >= 2 per axis)
+    constexpr int kPW = MW / 2 + 2, kPH = MH / 2 + 2;
+    constexpr int kYPer = POST ? (kPW * kPH + BX * BY - 1) / (BX * BY) : 1;
+    __shared__ R ys[POST ? kPW * kPH : 1];
+    int xI0[2], xI1[2];
+    R xw0[2], xw1[2];
+    int pI = 0, pJ = 0, PW = 0, PH = 0;
+    bool staged = false;
+    R yv_[kYPer];
+    if (POST) {
+      int a0, a1, b0, b1;
+      R u0, u1;
+      ext_weights<R>(rx0, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+      pI = a0;
+      ext_weights<R>(rx0 + RW - 1, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+      PW = a1 - pI + 1;
+      ext_weights<R>(ry0, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+      pJ = b0;
+      ext_weights<R>(ry0 + RH - 1, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+      PH = b1 - pJ + 1;
+      staged = PW <= kPW && PH <= kPH;  // the same for every thread
+#pragma unroll
+      for (int u = 0; u < kYPer; ++u) {
+        const int e = threadIdx.x + u * BX * BY;
+        const int jj = staged ? e / PW : 0, ii = staged ? e - jj * PW : 0;
+        yv_[u] = (staged && e < PW * PH) ? y[(pI + ii) + X.cnx * (pJ + jj)] : R(0);
+      }
+    }
+    asm volatile("" ::"v"(gv));  // the gate's wait comes after every load is issued
+    if (gv) return;
+    if (POST) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
+      if (staged) {
+#pragma unroll
+        for (int u = 0; u < kYPer; ++u) {
+          const int e = threadIdx.x + u * BX * BY;
+          if (e < PW * PH) ys[e] = yv_[u];
+        }
+        __syncthreads();
+      }
+    }
+    auto yv = [&](int I, int J) { return staged ? ys[(J - pJ) * PW + (I - pI)] : y[I + X.cnx * J]; };
+#pragma unroll
+    for (int b = 0; b < NR; ++b) {
+      const int lj = ty + BY * b;
+      const int j = ry0 + lj;
+      int J0 = 0, J1 = 0;
+      R wj0 = R(0), wj1 = R(0);
+      if (POST && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int q = (rx0 + ry0 + lj + c) & 1;
+        const int li = 2 * k + q;
+        dg[b][c] = R(1);  // inverse diagonal
+        if (lj < RH && li < RW) {
+          const int i = rx0 + li;
+          const R tw = cw[b][c], te = ce[b][c], ts = cs[b][c], tn = cn[b][c];
+          dg[b][c] = R(1) / (tw + te + ts + tn);
+          if (!(i > 0 && li > 0)) cw[b][c] = R(0);
+          if (!(i < nx - 1 && li < RW - 1)) ce[b][c] = R(0);
+          if (!(j > 0 && lj > 0)) cs[b][c] = R(0);
+          if (!(j < ny - 1 && lj < RH - 1)) cn[b][c] = R(0);
+          if (POST) {
+            // same products, in the same order, as the grid-wide prolongation
+            R v = R(0);
+            if (wj0 != R(0)) {
+              if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * yv(xI0[q], J0);
+              if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * yv(xI1[q], J0);
+            }
+            if (wj1 != R(0)) {
+              if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * yv(xI0[q], J1);
+              if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * yv(xI1[q], J1);
+            }
+            zc[c][lj][k] = zp[b][c] + v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    if (gv) return;
+    // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
+    // within its colour.  The thread's cell of colour c in row lj is
+    // li = 2k + ((rx0 + ry0 + lj + c) & 1).
+    int xI0[2], xI1[2];
+    R xw0[2], xw1[2];
+    // post-smoothing: the coarse values the region's prolongation reads are
+    // staged in LDS when the patch fits (factors >= 2 per axis)
+    constexpr int kPW = MW / 2 + 2, kPH = MH / 2 + 2;
+    __shared__ R ys[POST ? kPW * kPH : 1];
+    int pI = 0, pJ = 0, PW = 0;
+    bool staged = false;
+    if (POST) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
+      int a0, a1, b0, b1;
+      R u0, u1;
+      ext_weights<R>(rx0, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+      pI = a0;
+      ext_weights<R>(rx0 + RW - 1, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
+      PW = a1 - pI + 1;
+      ext_weights<R>(ry0, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+      pJ = b0;
+      ext_weights<R>(ry0 + RH - 1, X.sy, X.cny, X.interp, b0, u0, b1, u1);
+      const int PH = b1 - pJ + 1;
+      staged = PW <= kPW && PH <= kPH;  // the same for every thread
+      if (staged) {
+        for (int e = threadIdx.x; e < PW * PH; e += BX * BY) {
+          const int jj = e / PW, ii = e - jj * PW;
+          ys[e] = y[(pI + ii) + X.cnx * (pJ + jj)];
+        }
+        __syncthreads();
+      }
+    }
+    auto yv = [&](int I, int J) { return staged ? ys[(J - pJ) * PW + (I - pI)] : y[I + X.cnx * J]; };
+#pragma unroll
+    for (int b = 0; b < NR; ++b) {
+      const int lj = ty + BY * b;
+      const int j = ry0 + lj;
+      int J0 = 0, J1 = 0;
+      R wj0 = R(0), wj1 = R(0);
+      if (POST && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int q = (rx0 + ry0 + lj + c) & 1;
+        const int li = 2 * k + q;
+        cw[b][c] = ce[b][c] = cs[b][c] = cn[b][c] = R(0);
+        dg[b][c] = R(1);  // inverse diagonal
+        rr[b][c] = R(0);
+        if (lj < RH && li < RW) {
+          const int i = rx0 + li;
+          const int fx = i + (nx + 1) * j, fy = i + nx * j;
+          const R tw = L.tx[fx], te = L.tx[fx + 1], ts = L.ty[fy], tn = L.ty[fy + nx];
+          dg[b][c] = R(1) / (tw + te + ts + tn);
+          if (i > 0 && li > 0) cw[b][c] = tw;
+          if (i < nx - 1 && li < RW - 1) ce[b][c] = te;
+          if (j > 0 && lj > 0) cs[b][c] = ts;
+          if (j < ny - 1 && lj < RH - 1) cn[b][c] = tn;
+          rr[b][c] = r[i + nx * j];
+          if (POST) {
+            // same products, in the same order, as the grid-wide prolongation
+            R v = R(0);
+            if (wj0 != R(0)) {
+              if (xw0[q] != R(0)) v += (R(1) * wj0 * xw0[q]) * yv(xI0[q], J0);
+              if (xw1[q] != R(0)) v += (R(1) * wj0 * xw1[q]) * yv(xI1[q], J0);
+            }
+            if (wj1 != R(0)) {
+              if (xw0[q] != R(0)) v += (R(1) * wj1 * xw0[q]) * yv(xI0[q], J1);
+              if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * yv(xI1[q], J1);
+            }
+            zc[c][lj][k] = zin[i + nx * j] + v;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-
   // 2m+1 half sweeps, red (colour 0) first; neighbours are of the other
   // colour: (li - 1, li + 1) in the row, li in the rows above and below
   for (int h = 0; h < kHalo; ++h) {
