@@ -129,9 +129,13 @@ SGS = 0
 JACOBI = 1
 
 
+RECURSIVE = 0  # recursive multi-scale PCG (eq. 2.10)
+MGCG = 1       # Tatebe's multigrid preconditioner (eq. 2.9)
+
+
 def _opts(scale=4, min_side=8, m=0, max_outer=200, max_inner=200, max_levels=MAX_LEVELS, interp=LINEAR,
-          splitting=SGS):
-    return [scale, min_side, m, max_outer, max_inner, max_levels, interp, splitting]
+          splitting=SGS, cycle=RECURSIVE):
+    return [scale, min_side, m, max_outer, max_inner, max_levels, interp, splitting, cycle]
 
 
 def _axis_w(axis_weight):

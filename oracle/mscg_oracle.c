@@ -473,8 +473,14 @@ static double dot(int n, const double *a, const double *b) {
 
 static int pcg_level(or_problem *P, int k, const double *b, double *x, int x_is_zero, int max_iter);
 
+/* Coarse part of the preconditioner: 0 the recursive multi-scale form
+ * (eq. 2.10, A_c^-1 by an inner PCG), 1 Tatebe's multigrid form (eq. 2.9,
+ * M_{k+1}^-1 applied once).  Both end with the exact coarsest solve. */
+static int g_cycle = 0;
+
 /* z = M_k^-1 r, eq. 2.10 evaluated as m smoothing steps from zero, a coarse
- * correction E A_c^-1 R of the remaining residual, and m smoothing steps. */
+ * correction E A_c^-1 R of the remaining residual, and m smoothing steps
+ * (eq. 2.9 when g_cycle is 1). */
 static void precond(or_problem *P, int k, const double *r, double *z) {
   or_level *L = &P->lev[k], *C = &P->lev[k + 1];
   memset(z, 0, sizeof(double) * L->n);
@@ -484,6 +490,11 @@ static void precond(or_problem *P, int k, const double *r, double *z) {
   restrict_T(L, C, L->s, C->t); /* coarse right-hand side */
   if (k + 1 == P->nlev - 1) {
     oracle_cholesky_solve(C->n, C->chol, C->t, C->x);
+    P->calls[k + 1]++;
+  } else if (g_cycle == 1) {
+    /* Tatebe's multigrid preconditioner (eq. 2.9): W_k = E M_{k+1}^-1 R, one
+     * application of the next level's preconditioner instead of a PCG solve */
+    precond(P, k + 1, C->t, C->x);
     P->calls[k + 1]++;
   } else {
     memset(C->x, 0, sizeof(double) * C->n);
@@ -599,13 +610,15 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
  * 3-D), source f; per-face BC type and value.  rhs b_c = f_c |V_c| plus, on
  * each Dirichlet boundary face, T_b p_D.  Output p (n cells).
  * iopt: scale, min_side, m, max_outer, max_inner, max_levels, interp (0 linear,
- * 1 piecewise constant), splitting (0 symmetric Gauss-Seidel, 1 modified Jacobi);
- * non-positive entries take the defaults 4, 8, scale, 200, 200, 8, 0, 0.
+ * 1 piecewise constant), splitting (0 symmetric Gauss-Seidel, 1 modified Jacobi),
+ * cycle (0 recursive multi-scale PCG, eq. 2.10; 1 Tatebe's multigrid
+ * preconditioner, eq. 2.9); non-positive entries take the defaults 4, 8,
+ * scale, 200, 200, 8, 0, 0, 0.
  * flvl_opt: f (default 0.1).  axis_w: NULL for the uniform level plan, else
  * the per-axis weights of the aspect-ratio-aware plan. */
 int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
                  const double *kz, const double *f, const int bc_type[6], const double bc_value[6], double tol,
-                 const int iopt[8], const double *flvl_opt, double *p_out, or_stats *st, const double *axis_w) {
+                 const int iopt[9], const double *flvl_opt, double *p_out, or_stats *st, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
   int m = iopt && iopt[2] > 0 ? iopt[2] : scale;
@@ -614,6 +627,7 @@ int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double 
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
   g_split = iopt && iopt[7] == 1 ? 1 : 0;
+  g_cycle = iopt && iopt[8] == 1 ? 1 : 0;
   double flvl = flvl_opt && *flvl_opt > 0.0 ? *flvl_opt : 0.1;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
@@ -756,7 +770,7 @@ void oracle_restrict(int dim, const int fd[3], const int s[3], int interp, const
  * max_inner large runs the inner PCGs to their iteration cap; a 2-level
  * hierarchy has an exact coarse solve regardless). */
 int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const double *kx, const double *ky,
-                   const double *kz, const int bc_type[6], const int iopt[8], double flvl, double eps2,
+                   const double *kz, const int bc_type[6], const int iopt[9], double flvl, double eps2,
                    const double *r, double *z, const double *axis_w) {
   int scale = iopt && iopt[0] > 0 ? iopt[0] : 4;
   int min_side = iopt && iopt[1] > 0 ? iopt[1] : 8;
@@ -765,6 +779,7 @@ int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const doubl
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
   g_split = iopt && iopt[7] == 1 ? 1 : 0;
+  g_cycle = iopt && iopt[8] == 1 ? 1 : 0;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   or_problem P;

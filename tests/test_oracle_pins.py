@@ -602,3 +602,95 @@ def test_semi_coarsening_helps_anisotropic_problems():
     cube = synth.layered_3d(2, 32, n_layers=4)
     semi3 = oracle.solve(cube, axis_weight=(1, 1, 0.01))
     assert semi3.status == 0 and semi3.outer_iters <= 8
+
+
+# ------------------------------------------------- Tatebe's multigrid preconditioner (eq. 2.9)
+
+def ext_1d(nf, s, interp):
+    """Dense 1-D extension operator (fine nf cells from nf / s coarse cells), written out from
+    its definition: cell-centred linear interpolation with zero slope at the boundary, or
+    piecewise constant."""
+    nc = nf // s
+    E = np.zeros((nf, nc))
+    for i in range(nf):
+        if interp == oracle.CONSTANT:
+            E[i, i // s] = 1
+            continue
+        xi = (i + 0.5) / s - 0.5
+        if xi <= 0:
+            E[i, 0] = 1
+        elif xi >= nc - 1:
+            E[i, nc - 1] = 1
+        else:
+            b = int(np.floor(xi))
+            E[i, b] += 1 - (xi - b)
+            E[i, b + 1] += xi - b
+    return E
+
+
+@pytest.mark.parametrize("interp", [oracle.LINEAR, oracle.CONSTANT])
+def test_mgcg_preconditioner_is_eq_2_9(interp):
+    # three levels (32^2, 8^2, 2^2): M_2^-1 = A_2^-1 exactly, and each finer level applies
+    # M_k^-1 = H^m (E M_{k+1}^-1 R) (H^T)^m + sum_{j<2m} H^j P^-1 with H = P^-1 Q (eq. 2.9)
+    P = problem_2d((32, 32), lo=-2, hi=2, seed=11)
+    m = 2
+    hier = oracle.hierarchy_T(P, min_side=2, max_levels=3)
+    assert [d[:2] for d, *_ in hier] == [(32, 32), (8, 8), (2, 2)]
+    As = [dense_from_T(2, d, tx, ty) for d, tx, ty, _ in hier]
+    Minv = np.linalg.inv(As[2])
+    for k in (1, 0):
+        d = hier[k][0]
+        E = np.kron(ext_1d(d[1], 4, interp), ext_1d(d[0], 4, interp))
+        Pm, Qm = splitting_dense(As[k], d[0], d[1])
+        Pinv = np.linalg.inv(Pm)
+        H = Pinv @ Qm
+        Hm = np.linalg.matrix_power(H, m)
+        Minv = Hm @ (E @ Minv @ E.T) @ Hm.T + sum(np.linalg.matrix_power(H, j) @ Pinv for j in range(2 * m))
+    N = As[0].shape[0]
+    got = np.stack([oracle.precond(P, e, interp=interp, m=m, min_side=2, max_levels=3, cycle=oracle.MGCG)
+                    for e in np.eye(N)], axis=1)
+    assert np.allclose(got, Minv, rtol=0, atol=1e-10 * np.abs(Minv).max())
+    # Tatebe's condition (Section 2): symmetric positive definite
+    assert np.allclose(got, got.T, atol=1e-12 * np.abs(got).max())
+    assert np.linalg.eigvalsh((got + got.T) / 2).min() > 0
+    # with three levels the recursive form differs: its level-1 coarse part is a PCG solve
+    rec = oracle.precond(P, np.eye(N)[0], interp=interp, m=m, min_side=2, max_levels=3, eps2=1e-30)
+    assert np.abs(rec - got[:, 0]).max() > 1e-6 * np.abs(got[:, 0]).max()
+
+
+def test_mgcg_two_levels_is_the_recursive_method():
+    # with one coarse level both forms use the exact coarse inverse (eq. 2.9 with M_1 = A_1, eq. 2.10)
+    P = problem_2d((64, 64), lo=-3, hi=3, seed=4)
+    a = oracle.solve(P, tol=1e-10, max_levels=2)
+    b = oracle.solve(P, tol=1e-10, max_levels=2, cycle=oracle.MGCG)
+    assert a.outer_iters == b.outer_iters and np.array_equal(a.p, b.p)
+
+
+@pytest.mark.parametrize("n,interp", [((32, 32), oracle.LINEAR), ((64, 32), oracle.LINEAR),
+                                      ((64, 64), oracle.CONSTANT)])
+def test_mgcg_solve_matches_dense_solution(n, interp):
+    P = problem_2d(n, lo=-2, hi=2, seed=9)
+    h = (1 / n[0], 1 / n[1], 1)
+    tx, ty, _ = oracle.face_T(2, P.n, h, P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, P.n, tx, ty)
+    x = np.linalg.solve(A, rhs(P, tx, ty))
+    r = oracle.solve(P, tol=1e-10, min_side=2, interp=interp, cycle=oracle.MGCG)
+    assert r.status == 0 and r.nlev >= 3
+    assert r.rel_residual_true < 1e-10
+    assert np.linalg.norm(r.p - x) / np.linalg.norm(x) < 1e-8
+    # every inner level is visited once per application of the level above; no inner CG iterations
+    assert r.level_iters[1:] == [0] * (r.nlev - 1)
+    assert r.level_calls[1] == r.outer_iters
+    for k in range(2, r.nlev):
+        assert r.level_calls[k] == r.level_calls[k - 1]
+
+
+def test_mgcg_needs_more_iterations_than_recursive():
+    # Section 4 expectation: Tatebe's algorithm takes more outer iterations than the recursive
+    # multi-scale PCG.  On these smoothed fields the gap shows with light smoothing (m = 1: 26
+    # against 24 at 256^2); with m = 4 both take 12.
+    P = synth.smoothed_lognormal_2d(2, 256, lo=-3, hi=3)
+    rec = oracle.solve(P, tol=1e-10, m=1)
+    mg = oracle.solve(P, tol=1e-10, m=1, cycle=oracle.MGCG)
+    assert rec.status == 0 and mg.status == 0
+    assert mg.outer_iters > rec.outer_iters
