@@ -66,6 +66,13 @@ enum { MSCG_INTERP_LINEAR = 0, MSCG_INTERP_CONSTANT = 1 };
  * P = (D+L) D^-1 (D+U); or modified Jacobi, P = 2D, fully parallel (every
  * inner level then runs host-driven with grid-wide kernels). */
 enum { MSCG_SPLIT_SGS = 0, MSCG_SPLIT_JACOBI = 1 };
+/* Coarse part of the preconditioner on the inner levels.  RECURSIVE: the
+ * recursive multi-scale PCG of eq. 2.10, A_c^-1 applied by an inner PCG on
+ * each coarse level.  MGCG: Tatebe's multigrid preconditioner of eq. 2.9,
+ * the next level's preconditioner M_{k+1}^-1 applied once (one V-shaped pass
+ * per outer iteration, no inner PCG).  Both end with the exact coarsest
+ * solve.  With MGCG every inner level runs host-driven with grid-wide kernels. */
+enum { MSCG_CYCLE_RECURSIVE = 0, MSCG_CYCLE_MGCG = 1 };
 
 typedef struct {
   int dim;            /* 2 or 3 */
@@ -95,6 +102,7 @@ typedef struct {
   double axis_weight[3];  /* permeability scale per axis for that plan (e.g. 1, 1, kz/kx), default 1 */
   int splitting;          /* operator splitting A = P - Q of the smoother (eq. 2.3, Section 3):
                              MSCG_SPLIT_SGS (default) or MSCG_SPLIT_JACOBI */
+  int cycle;              /* MSCG_CYCLE_RECURSIVE (default, eq. 2.10) or MSCG_CYCLE_MGCG (eq. 2.9) */
 } mscg_options;
 
 typedef struct {

@@ -88,6 +88,7 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   int maxl = o->max_levels < 1 ? 1 : (o->max_levels > MSCG_MAX_LEVELS ? MSCG_MAX_LEVELS : o->max_levels);
   if (o->semi_coarsen != 0 && o->semi_coarsen != 1) return fail(MSCG_E_ARG, "semi_coarsen must be 0 or 1");
   if (o->splitting != MSCG_SPLIT_SGS && o->splitting != MSCG_SPLIT_JACOBI) return fail(MSCG_E_ARG, "bad splitting");
+  if (o->cycle != MSCG_CYCLE_RECURSIVE && o->cycle != MSCG_CYCLE_MGCG) return fail(MSCG_E_ARG, "bad cycle");
   if (o->semi_coarsen)
     for (int a = 0; a < g->dim; ++a)
       if (!(o->axis_weight[a] > 0.0)) return fail(MSCG_E_ARG, "axis_weight[%d] must be > 0", a);
@@ -286,7 +287,12 @@ double small_level_flops(const mscg_problem* P) {
   return (9.0 * (2.0 * m + 1.0) + 45.0) * n + 4.0 * S.ny * S.nz * C.nx + 2.0 * nc * nc;
 }
 
-// Coarse part of the preconditioner on level k: y_{k+1} = A_{k+1}^-1 g.
+template <typename R>
+R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, R* const* xs, R* const* rs,
+                R* const* zs, R* const* ps, R* const* qs, int* rc, const int* gate, int* nfused);
+
+// Coarse part of the preconditioner on level k: y_{k+1} = A_{k+1}^-1 g, or
+// y_{k+1} = M_{k+1}^-1 g with Tatebe's multigrid form.
 template <typename R>
 int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* const* zs, R* const* ps, R* const* qs,
                       const int* gate) {
@@ -294,6 +300,20 @@ int coarse_correction(mscg_problem* P, int k, R* const* xs, R* const* rs, R* con
   if (kc == P->nlev - 1) {
     HIP_TRY(launch_coarse_solve<R>(P->Ainv, rs[kc], xs[kc], P->ncoarse, P->stream, gate));
     if (!gate) P->calls[kc]++;  // queued-ahead iterations are counted by cg_loop
+    return MSCG_OK;
+  }
+  if (P->o.cycle == MSCG_CYCLE_MGCG) {
+    // eq. 2.9: the next level's preconditioner applied once to g, in place of
+    // its PCG solve.  Its pre-smoothing iterate goes to z_{k+1}; its result
+    // is wanted in x_{k+1}, which also serves as its second work vector.
+    Lv<R> Lc;
+    if constexpr (std::is_same<R, float>::value) Lc = lv32(P, kc);
+    else Lc = lv64(P, kc);
+    int rc = MSCG_OK;
+    R* out = precond_host<R>(P, kc, Lc, rs[kc], zs[kc], xs[kc], xs, rs, zs, ps, qs, &rc, gate, nullptr);
+    if (rc) return rc;
+    if (out != xs[kc]) HIP_TRY(launch_copy<R>(out, xs[kc], Lc.n, P->stream));
+    if (!gate) P->calls[kc]++;
     return MSCG_OK;
   }
   if (kc >= P->ks) {
@@ -633,6 +653,7 @@ void mscg_default_options(mscg_options* o) {
   o->semi_coarsen = 0;
   o->axis_weight[0] = o->axis_weight[1] = o->axis_weight[2] = 1.0;
   o->splitting = MSCG_SPLIT_SGS;
+  o->cycle = MSCG_CYCLE_RECURSIVE;
 }
 
 const char* mscg_last_error(void) { return g_err.c_str(); }
@@ -695,7 +716,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   if (rc) { mscg_destroy_problem(P); return rc; }
   const int sn = small_n();
   P->ks = P->nlev;  // no small level
-  if (P->o.splitting == MSCG_SPLIT_SGS)  // the one-workgroup solvers smooth by red-black SGS only
+  // the one-workgroup solvers smooth by red-black SGS only, and run an inner PCG
+  if (P->o.splitting == MSCG_SPLIT_SGS && P->o.cycle == MSCG_CYCLE_RECURSIVE)
     for (int l = 1; l < P->nlev - 1; ++l)
       if (P->lev[l].n <= sn) { P->ks = l; break; }
   for (int l = 0; l < P->nlev; ++l) {

@@ -19,6 +19,7 @@ E_ARG, E_NOMEM, E_DEVICE, E_BREAKDOWN, E_STATE, E_SINGULAR = -1, -2, -3, -4, -5,
 NEUMANN, DIRICHLET = 0, 1
 FP64, MIXED = 0, 1
 SPLIT_SGS, SPLIT_JACOBI = 0, 1
+CYCLE_RECURSIVE, CYCLE_MGCG = 0, 1
 INTERP_LINEAR, INTERP_CONSTANT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_BREAKDOWN",
@@ -41,7 +42,7 @@ class _Options(ctypes.Structure):
                 ("level_factor", ctypes.c_double), ("min_coarse_side", ctypes.c_int), ("max_levels", ctypes.c_int),
                 ("max_outer_iters", ctypes.c_int), ("max_inner_iters", ctypes.c_int), ("interp", ctypes.c_int),
                 ("flexible", ctypes.c_int), ("inner_rel_floor", ctypes.c_double), ("semi_coarsen", ctypes.c_int),
-                ("axis_weight", ctypes.c_double * 3), ("splitting", ctypes.c_int)]
+                ("axis_weight", ctypes.c_double * 3), ("splitting", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -167,6 +168,7 @@ class Options:
     semi_coarsen: int = 0
     axis_weight: tuple = (1.0, 1.0, 1.0)
     splitting: int = 0  # SPLIT_SGS or SPLIT_JACOBI
+    cycle: int = 0  # CYCLE_RECURSIVE (eq. 2.10) or CYCLE_MGCG (eq. 2.9)
 
     def _c(self) -> _Options:
         o = _Options()

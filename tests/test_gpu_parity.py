@@ -457,3 +457,69 @@ def test_full_size_1024_matches_oracle():
         assert st.status == 0 and st.rel_residual_true <= 1e-10
         assert err <= 1e-8
         assert abs(st.outer_iters - ref.outer_iters) <= 2
+
+
+# ------------------------------------------- Tatebe's multigrid preconditioner (eq. 2.9)
+
+@pytest.mark.parametrize("name,make,opt", [
+    ("small32_3lev", lambda: synth.small_case(2), {"min_coarse_side": 2}),
+    ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
+    ("layered32_const", lambda: synth.layered_3d(2, 32, n_layers=8), {"interp": 1, "min_coarse_side": 2}),
+], ids=["small32_3lev", "smooth256", "layered32_const"])
+def test_mgcg_preconditioner(name, make, opt):
+    """M_0^-1 r of eq. 2.9 (one pass down and up the hierarchy, no inner PCG):
+    only rounding differs from the oracle."""
+    from paper_math_9809043_amd import mscg
+    case(f"MGCG preconditioner {name}")
+    torch = _torch()
+    P = make()
+    prob = make_problem(P, cycle=mscg.CYCLE_MGCG, **opt)
+    assert prob.n_levels >= 3
+    r = np.random.default_rng(8).standard_normal(P.N)
+    z = torch.empty(P.N, dtype=torch.float64, device="cuda")
+    prob.apply_preconditioner(dev_tensor(r), z, 0.0)
+    zo = oracle.precond(P, r, cycle=oracle.MGCG, **oracle_opts(opt))
+    err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"  rel diff {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
+MGCG_CASES = [
+    ("small32_3lev", lambda: synth.small_case(4), {"min_coarse_side": 2}),
+    ("ragged176x48", lambda: synth.smoothed_lognormal_2d(4, 176, 48, lo=-3, hi=3), {"min_coarse_side": 2}),
+    ("smooth256", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {}),
+    ("smooth512", lambda: synth.smoothed_lognormal_2d(5, 512, lo=-3, hi=3), {}),
+    ("rect288x160_const", lambda: synth.smoothed_lognormal_2d(7, 288, 160, lo=-2, hi=2), {"interp": 1}),
+    ("layered32_const", lambda: synth.layered_3d(2, 32, n_layers=8), {"interp": 1, "min_coarse_side": 2}),
+    ("smooth256_jacobi", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"jacobi": True}),
+    ("smooth1024", lambda: synth.smoothed_lognormal_2d(0, 1024, lo=-3.0, hi=3.0, tol=1e-10), {}),
+]
+
+
+@pytest.mark.parametrize("name,make,opt", MGCG_CASES, ids=[c[0] for c in MGCG_CASES])
+def test_mgcg_parity(name, make, opt):
+    """Full solves with Tatebe's preconditioner, FP64 and mixed, against the
+    oracle's: residual, solution, outer iterations, and one visit of every
+    inner level per application of the level above."""
+    from paper_math_9809043_amd import mscg
+    case(f"MGCG solve {name}")
+    P = make()
+    opt = dict(opt)
+    jac = opt.pop("jacobi", False)
+    gopt = dict(opt, cycle=mscg.CYCLE_MGCG)
+    oopt = dict(oracle_opts(opt), cycle=oracle.MGCG)
+    if jac:
+        gopt["splitting"] = mscg.SPLIT_JACOBI
+        oopt["splitting"] = oracle.JACOBI
+    ref = oracle.solve(P, **oopt)
+    assert ref.status == 0 and ref.nlev >= 3
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec, **gopt)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: outer {st.outer_iters} (oracle {ref.outer_iters}) calls "
+              f"{st.level_calls} (oracle {ref.level_calls}) res {st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
+        assert list(st.level_iters[1:]) == [0] * (st.n_levels - 1)
+        assert [st.level_calls[k] for k in range(1, st.n_levels)] == [st.outer_iters] * (st.n_levels - 1)
