@@ -254,6 +254,22 @@ def main():
         print(f"[bench] smooth1024 modified Jacobi: fp64 {wallj:.1f} ms (outer {stj.outer_iters}, levels "
               f"{stj.level_iters})", flush=True)
 
+    if not args.no_3d and args.workload == "smooth1024":
+        # comparison: Tatebe's multigrid preconditioner (eq. 2.9, one pass down and up
+        # the same hierarchy per outer iteration, no inner PCG) on the same problem
+        res = {}
+        for label, prec in (("fp64", mscg.FP64), ("mixed", mscg.MIXED)):
+            optg = dict(W["opt"])
+            optg.update(cycle=mscg.CYCLE_MGCG, precision=prec)
+            _, stg, wallg, solveg, _ = run_gpu(P, optg, 5, 1)
+            res[label] = {"value": round(P.N / (wallg * 1e-3), 1), "ms_per_step": round(wallg, 3),
+                          "solve_ms": round(solveg, 3), "outer_iters": stg.outer_iters,
+                          "level_calls": stg.level_calls, "rel_residual_true": stg.rel_residual_true}
+            print(f"[bench] smooth1024 MGCG {label}: {wallg:.2f} ms/step (outer {stg.outer_iters}) res "
+                  f"{stg.rel_residual_true:.2e}", flush=True)
+        extra["smooth1024_mgcg"] = dict({"workload": W["desc"] + "; Tatebe's multigrid preconditioner (eq. 2.9) "
+                                         "in place of the inner PCGs"}, **res)
+
     value = P.N / (wall_ms * 1e-3)
     line = {
         "metric": "unknowns solved/s to 1e-10 resid (set-up + solve), FP64 plain method; mixed alongside",
