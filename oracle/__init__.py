@@ -131,6 +131,7 @@ JACOBI = 1
 
 RECURSIVE = 0  # recursive multi-scale PCG (eq. 2.10)
 MGCG = 1       # Tatebe's multigrid preconditioner (eq. 2.9)
+POLY = 2       # polynomial preconditioner (Section 2.1, W = P^-1)
 
 
 def _opts(scale=4, min_side=8, m=0, max_outer=200, max_inner=200, max_levels=MAX_LEVELS, interp=LINEAR,

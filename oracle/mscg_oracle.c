@@ -475,7 +475,8 @@ static int pcg_level(or_problem *P, int k, const double *b, double *x, int x_is_
 
 /* Coarse part of the preconditioner: 0 the recursive multi-scale form
  * (eq. 2.10, A_c^-1 by an inner PCG), 1 Tatebe's multigrid form (eq. 2.9,
- * M_{k+1}^-1 applied once).  Both end with the exact coarsest solve. */
+ * M_{k+1}^-1 applied once); both end with the exact coarsest solve.  2 the
+ * polynomial preconditioner (Section 2.1, W = P^-1), which has no coarse part. */
 static int g_cycle = 0;
 
 /* z = M_k^-1 r, eq. 2.10 evaluated as m smoothing steps from zero, a coarse
@@ -484,6 +485,13 @@ static int g_cycle = 0;
 static void precond(or_problem *P, int k, const double *r, double *z) {
   or_level *L = &P->lev[k], *C = &P->lev[k + 1];
   memset(z, 0, sizeof(double) * L->n);
+  if (g_cycle == 2) {
+    /* polynomial preconditioner (Section 2.1): W = P^-1 in eq. 2.6 makes M^-1
+     * the first 2m+1 terms of the series of eq. 2.4, i.e. 2m+1 steps of the
+     * splitting from zero; no coarse level is used */
+    smooth(L, r, z, 2 * P->m + 1);
+    return;
+  }
   smooth(L, r, z, P->m);
   apply_A(L, z, L->s);
   for (int i = 0; i < L->n; ++i) L->s[i] = r[i] - L->s[i];
@@ -612,7 +620,8 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
  * iopt: scale, min_side, m, max_outer, max_inner, max_levels, interp (0 linear,
  * 1 piecewise constant), splitting (0 symmetric Gauss-Seidel, 1 modified Jacobi),
  * cycle (0 recursive multi-scale PCG, eq. 2.10; 1 Tatebe's multigrid
- * preconditioner, eq. 2.9); non-positive entries take the defaults 4, 8,
+ * preconditioner, eq. 2.9; 2 polynomial preconditioner, Section 2.1);
+ * non-positive entries take the defaults 4, 8,
  * scale, 200, 200, 8, 0, 0, 0.
  * flvl_opt: f (default 0.1).  axis_w: NULL for the uniform level plan, else
  * the per-axis weights of the aspect-ratio-aware plan. */
@@ -627,7 +636,7 @@ int oracle_solve(int dim, const int n[3], const double Ldom_in[3], const double 
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
   g_split = iopt && iopt[7] == 1 ? 1 : 0;
-  g_cycle = iopt && iopt[8] == 1 ? 1 : 0;
+  g_cycle = iopt && (iopt[8] == 1 || iopt[8] == 2) ? iopt[8] : 0;
   double flvl = flvl_opt && *flvl_opt > 0.0 ? *flvl_opt : 0.1;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
@@ -779,7 +788,7 @@ int oracle_precond(int dim, const int n[3], const double Ldom_in[3], const doubl
   int max_levels = iopt && iopt[5] > 0 ? iopt[5] : OR_MAX_LEVELS;
   g_interp = iopt && iopt[6] == 1 ? 1 : 0;
   g_split = iopt && iopt[7] == 1 ? 1 : 0;
-  g_cycle = iopt && iopt[8] == 1 ? 1 : 0;
+  g_cycle = iopt && (iopt[8] == 1 || iopt[8] == 2) ? iopt[8] : 0;
   double Ldom[3] = {1.0, 1.0, 1.0};
   if (Ldom_in) for (int a = 0; a < 3; ++a) if (Ldom_in[a] > 0.0) Ldom[a] = Ldom_in[a];
   or_problem P;

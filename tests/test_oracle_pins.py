@@ -694,3 +694,52 @@ def test_mgcg_needs_more_iterations_than_recursive():
     mg = oracle.solve(P, tol=1e-10, m=1, cycle=oracle.MGCG)
     assert rec.status == 0 and mg.status == 0
     assert mg.outer_iters > rec.outer_iters
+
+
+# ------------------------------------------------- polynomial preconditioner (Section 2.1)
+
+@pytest.mark.parametrize("splitting", [oracle.SGS, oracle.JACOBI])
+def test_polynomial_preconditioner_is_the_series(splitting):
+    # W = P^-1: M^-1 is the first 2m+1 terms of the series of eq. 2.4, sum_{j<=2m} (P^-1 Q)^j P^-1
+    P = problem_2d((16, 16), lo=-3, hi=3, seed=3)
+    m = 2
+    A, _, _, Pm, Qm = two_level_dense(P, oracle.LINEAR, m)
+    if splitting == oracle.JACOBI:
+        D = np.diag(np.diag(A))
+        Pm, Qm = 2 * D, D - (A - D)
+    Pinv = np.linalg.inv(Pm)
+    H = Pinv @ Qm
+    series = sum(np.linalg.matrix_power(H, j) @ Pinv for j in range(2 * m + 1))
+    N = A.shape[0]
+    got = np.stack([oracle.precond(P, e, m=m, max_levels=2, min_side=2, splitting=splitting, cycle=oracle.POLY)
+                    for e in np.eye(N)], axis=1)
+    assert np.allclose(got, series, rtol=0, atol=1e-11 * np.abs(series).max())
+    assert np.allclose(got, got.T, atol=1e-12 * np.abs(got).max())
+    assert np.linalg.eigvalsh((got + got.T) / 2).min() > 0
+
+
+@pytest.mark.parametrize("n", [(32, 32), (64, 32)])
+def test_polynomial_solve_matches_dense_solution(n):
+    P = problem_2d(n, lo=-2, hi=2, seed=6)
+    h = (1 / n[0], 1 / n[1], 1)
+    tx, ty, _ = oracle.face_T(2, P.n, h, P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, P.n, tx, ty)
+    x = np.linalg.solve(A, rhs(P, tx, ty))
+    r = oracle.solve(P, tol=1e-10, min_side=2, cycle=oracle.POLY, max_outer=2000)
+    assert r.status == 0 and r.rel_residual_true < 1e-10
+    assert np.linalg.norm(r.p - x) / np.linalg.norm(x) < 1e-8
+    # one level only: no coarse level is visited
+    assert r.level_calls[1:] == [0] * (r.nlev - 1) and r.level_iters[1:] == [0] * (r.nlev - 1)
+
+
+def test_polynomial_iterations_grow_with_the_grid():
+    # Section 2.1: with a purely local preconditioner the iteration count grows rapidly with
+    # the dimension of the system (here about twofold per doubling of the side), unlike the
+    # recursive method's nearly constant count
+    its = []
+    for n in (32, 64, 128):
+        P = synth.smoothed_lognormal_2d(2, n, lo=-3, hi=3)
+        r = oracle.solve(P, tol=1e-10, cycle=oracle.POLY, max_outer=2000)
+        assert r.status == 0
+        its.append(r.outer_iters)
+    assert its[1] > 1.6 * its[0] and its[2] > 1.6 * its[1]
