@@ -71,8 +71,11 @@ enum { MSCG_SPLIT_SGS = 0, MSCG_SPLIT_JACOBI = 1 };
  * each coarse level.  MGCG: Tatebe's multigrid preconditioner of eq. 2.9,
  * the next level's preconditioner M_{k+1}^-1 applied once (one V-shaped pass
  * per outer iteration, no inner PCG).  Both end with the exact coarsest
- * solve.  With MGCG every inner level runs host-driven with grid-wide kernels. */
-enum { MSCG_CYCLE_RECURSIVE = 0, MSCG_CYCLE_MGCG = 1 };
+ * solve.  With MGCG every inner level runs host-driven with grid-wide kernels.
+ * POLY: the polynomial preconditioner of Section 2.1 (W = P^-1), 2m+1 steps
+ * of the splitting from zero on the finest level; the coarse levels are
+ * still planned and set up but never visited. */
+enum { MSCG_CYCLE_RECURSIVE = 0, MSCG_CYCLE_MGCG = 1, MSCG_CYCLE_POLY = 2 };
 
 typedef struct {
   int dim;            /* 2 or 3 */
@@ -102,7 +105,8 @@ typedef struct {
   double axis_weight[3];  /* permeability scale per axis for that plan (e.g. 1, 1, kz/kx), default 1 */
   int splitting;          /* operator splitting A = P - Q of the smoother (eq. 2.3, Section 3):
                              MSCG_SPLIT_SGS (default) or MSCG_SPLIT_JACOBI */
-  int cycle;              /* MSCG_CYCLE_RECURSIVE (default, eq. 2.10) or MSCG_CYCLE_MGCG (eq. 2.9) */
+  int cycle;              /* MSCG_CYCLE_RECURSIVE (default, eq. 2.10), MSCG_CYCLE_MGCG (eq. 2.9) or
+                             MSCG_CYCLE_POLY (Section 2.1) */
 } mscg_options;
 
 typedef struct {

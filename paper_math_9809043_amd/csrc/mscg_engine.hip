@@ -88,7 +88,8 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   int maxl = o->max_levels < 1 ? 1 : (o->max_levels > MSCG_MAX_LEVELS ? MSCG_MAX_LEVELS : o->max_levels);
   if (o->semi_coarsen != 0 && o->semi_coarsen != 1) return fail(MSCG_E_ARG, "semi_coarsen must be 0 or 1");
   if (o->splitting != MSCG_SPLIT_SGS && o->splitting != MSCG_SPLIT_JACOBI) return fail(MSCG_E_ARG, "bad splitting");
-  if (o->cycle != MSCG_CYCLE_RECURSIVE && o->cycle != MSCG_CYCLE_MGCG) return fail(MSCG_E_ARG, "bad cycle");
+  if (o->cycle != MSCG_CYCLE_RECURSIVE && o->cycle != MSCG_CYCLE_MGCG && o->cycle != MSCG_CYCLE_POLY)
+    return fail(MSCG_E_ARG, "bad cycle");
   if (o->semi_coarsen)
     for (int a = 0; a < g->dim; ++a)
       if (!(o->axis_weight[a] > 0.0)) return fail(MSCG_E_ARG, "axis_weight[%d] must be > 0", a);
@@ -368,6 +369,23 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
     if (e != hipSuccess && *rc == MSCG_OK) *rc = fail(MSCG_E_DEVICE, "precond level %d: %s", k, hipGetErrorString(e));
     return e == hipSuccess;
   };
+  if (P->o.cycle == MSCG_CYCLE_POLY) {
+    // polynomial preconditioner (Section 2.1): W = P^-1 turns eq. 2.6 into
+    // 2m+1 steps of the splitting from zero on this level alone
+    const int steps = 2 * m + 1;
+    if (P->o.splitting == MSCG_SPLIT_JACOBI) {
+      R* cur = z;
+      R* nxt = w;
+      for (int step = 0; step < steps; ++step) {
+        if (!chk(launch_mjac_step<R>(L, r, cur, nxt, step == 0, P->stream, gate))) return nullptr;
+        std::swap(cur, nxt);
+      }
+      return cur;
+    }
+    for (int h = 0; h <= 2 * steps; ++h)
+      if (!chk(launch_gs_half<R>(L, r, z, h & 1, h == 0, P->stream, gate))) return nullptr;
+    return z;
+  }
   if (P->o.splitting == MSCG_SPLIT_JACOBI) {
     // m modified Jacobi steps from zero, alternating between z and w; the
     // restriction's residual goes to the buffer not holding the iterate

@@ -19,7 +19,7 @@ E_ARG, E_NOMEM, E_DEVICE, E_BREAKDOWN, E_STATE, E_SINGULAR = -1, -2, -3, -4, -5,
 NEUMANN, DIRICHLET = 0, 1
 FP64, MIXED = 0, 1
 SPLIT_SGS, SPLIT_JACOBI = 0, 1
-CYCLE_RECURSIVE, CYCLE_MGCG = 0, 1
+CYCLE_RECURSIVE, CYCLE_MGCG, CYCLE_POLY = 0, 1, 2
 INTERP_LINEAR, INTERP_CONSTANT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_BREAKDOWN",
@@ -168,7 +168,7 @@ class Options:
     semi_coarsen: int = 0
     axis_weight: tuple = (1.0, 1.0, 1.0)
     splitting: int = 0  # SPLIT_SGS or SPLIT_JACOBI
-    cycle: int = 0  # CYCLE_RECURSIVE (eq. 2.10) or CYCLE_MGCG (eq. 2.9)
+    cycle: int = 0  # CYCLE_RECURSIVE (eq. 2.10), CYCLE_MGCG (eq. 2.9) or CYCLE_POLY (Section 2.1)
 
     def _c(self) -> _Options:
         o = _Options()

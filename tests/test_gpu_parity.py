@@ -523,3 +523,50 @@ def test_mgcg_parity(name, make, opt):
         assert abs(st.outer_iters - ref.outer_iters) <= 2
         assert list(st.level_iters[1:]) == [0] * (st.n_levels - 1)
         assert [st.level_calls[k] for k in range(1, st.n_levels)] == [st.outer_iters] * (st.n_levels - 1)
+
+
+# ------------------------------------------- polynomial preconditioner (Section 2.1)
+
+POLY_CASES = [
+    ("small32", lambda: synth.small_case(5), {}),
+    ("rect96x40", lambda: synth.smoothed_lognormal_2d(4, 96, 40, lo=-3, hi=3), {}),
+    ("smooth128", lambda: synth.smoothed_lognormal_2d(2, 128, lo=-3, hi=3), {}),
+    ("smooth64_jacobi", lambda: synth.smoothed_lognormal_2d(2, 64, lo=-3, hi=3), {"jacobi": True}),
+    ("layered16", lambda: synth.layered_3d(2, 16, n_layers=4), {"min_coarse_side": 2}),
+]
+
+
+@pytest.mark.parametrize("name,make,opt", POLY_CASES, ids=[c[0] for c in POLY_CASES])
+def test_polynomial_parity(name, make, opt):
+    """W = P^-1 (2m+1 steps of the splitting from zero): the preconditioner
+    itself to rounding, and full solves in FP64 and mixed against the oracle's."""
+    from paper_math_9809043_amd import mscg
+    case(f"polynomial preconditioner {name}")
+    torch = _torch()
+    P = make()
+    opt = dict(opt)
+    jac = opt.pop("jacobi", False)
+    gopt = dict(opt, cycle=mscg.CYCLE_POLY, max_outer_iters=3000)
+    oopt = dict(oracle_opts(opt), cycle=oracle.POLY, max_outer=3000)
+    if jac:
+        gopt["splitting"] = mscg.SPLIT_JACOBI
+        oopt["splitting"] = oracle.JACOBI
+    prob = make_problem(P, **gopt)
+    r = np.random.default_rng(3).standard_normal(P.N)
+    z = torch.empty(P.N, dtype=torch.float64, device="cuda")
+    prob.apply_preconditioner(dev_tensor(r), z, 0.0)
+    zo = oracle.precond(P, r, **oopt)
+    assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) < 1e-12
+    ref = oracle.solve(P, **oopt)
+    assert ref.status == 0
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec, **gopt)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: outer {st.outer_iters} (oracle {ref.outer_iters}) res "
+              f"{st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert list(st.level_calls[1:]) == [0] * (st.n_levels - 1)
+        # FP64 follows the oracle's iteration to rounding; the FP32 preconditioner may move the
+        # count of this slowly converging iteration a little further
+        assert abs(st.outer_iters - ref.outer_iters) <= (2 if prec == mscg.FP64 else max(2, ref.outer_iters // 10))
