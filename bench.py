@@ -92,6 +92,46 @@ def run_gpu(P, opt, steps, warmup, time_small=False):
     return prob, st, wall_ms, solve_ms, p
 
 
+def run_scaling(sides, mgcg=True):
+    """Time against N (the paper's scaling study, Section 4): the config-1 generator (log10 k ~
+    U[-1,1], 3x3 box mean) on n x n grids, tol 1e-10, set-up + solve per step, FP64 and mixed,
+    plus Tatebe's preconditioner in FP64 for comparison."""
+    import math
+    from paper_math_9809043_amd import mscg, synth
+    rows = []
+    for n in sides:
+        P = synth.smoothed_lognormal_2d(0, n, lo=-1.0, hi=1.0, tol=1e-10, name=f"c1_{n}")
+        steps, warm = (3, 1) if n <= 2048 else (2, 1)
+        row = {"side": n, "unknowns": P.N}
+        variants = [("fp64", {}), ("mixed", {"precision": mscg.MIXED})]
+        if mgcg:
+            variants.append(("mgcg_fp64", {"cycle": mscg.CYCLE_MGCG}))
+        for label, opt in variants:
+            _, st, wall, solve, _ = run_gpu(P, opt, steps, warm)
+            row[label] = {"ms_per_step": round(wall, 3), "solve_ms": round(solve, 3),
+                          "unknowns_per_s": round(P.N / (wall * 1e-3), 1), "ns_per_unknown": round(wall * 1e6 / P.N, 3),
+                          "outer_iters": st.outer_iters, "level_iters": st.level_iters, "status": st.status,
+                          "rel_residual_true": st.rel_residual_true}
+        print(f"[bench] scaling {n}^2: fp64 {row['fp64']['ms_per_step']:.2f} ms (outer {row['fp64']['outer_iters']}), "
+              f"mixed {row['mixed']['ms_per_step']:.2f} ms"
+              + (f", MGCG {row['mgcg_fp64']['ms_per_step']:.2f} ms (outer {row['mgcg_fp64']['outer_iters']})"
+                 if mgcg else ""), flush=True)
+        rows.append(row)
+    # slope of log(time) against log(N) over the grids of 2^18 unknowns and more, where the
+    # per-launch latency of the coarse levels no longer sets the time
+    big = [r for r in rows if r["unknowns"] >= 1 << 18]
+    fit = {}
+    if len(big) >= 2:
+        for label in [k for k in rows[0] if k not in ("side", "unknowns")]:
+            xs = [math.log(r["unknowns"]) for r in big]
+            ys = [math.log(r[label]["ms_per_step"]) for r in big]
+            mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
+            fit[label] = round(sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs), 3)
+    return {"workload": "2-D 5-point FV, n x n, log10 k ~ U[-1,1] i.i.d. then 3x3 box-smoothed, Dirichlet p=0/1 on x, "
+                        "f ~ N(0,1), tol 1e-10, seed 0; set-up + solve per step",
+            "rows": rows, "time_exponent_vs_N_from_2^18": fit}
+
+
 def run_serving(count):
     """Serving stream: sides U{64,128,256,512}, contrast 1e6, tol 1e-8, mixed precision.
     Saturation throughput from a burst, then Poisson arrivals at 0.7x that rate."""
@@ -127,6 +167,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-scaling", action="store_true")
+    ap.add_argument("--scaling-sides", default="32,64,128,256,512,1024,2048,4096")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one process, one MI355X).",
@@ -270,6 +312,10 @@ def main():
         extra["smooth1024_mgcg"] = dict({"workload": W["desc"] + "; Tatebe's multigrid preconditioner (eq. 2.9) "
                                          "in place of the inner PCGs"}, **res)
 
+    scaling = None
+    if not args.no_scaling:
+        scaling = run_scaling([int(v) for v in args.scaling_sides.split(",") if v])
+
     value = P.N / (wall_ms * 1e-3)
     line = {
         "metric": "unknowns solved/s to 1e-10 resid (set-up + solve), FP64 plain method; mixed alongside",
@@ -286,6 +332,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "extra_workloads": extra,
+        "time_vs_N": scaling,
     }
     print(json.dumps(line), flush=True)
 
