@@ -21,6 +21,13 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 PEAK_FP64_CU_TFLOPS = 78.6 / 256  # MI355X FP64 vector peak per CU (256 CUs)
 
+# HBM bytes per launch on the smooth1024 FP64 workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE,
+# over `bench.py --kernels-only 10`; FETCH_SIZE scaled by 1.9993 (what the counter reads for a plain
+# copy of known size), WRITE_SIZE by 1.0.  Taken for the kernels as they stand; a kernel change
+# invalidates its figure.
+PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 361258, "smooth_pre": 37043456, "smooth_post": 101605558,
+                          "spmv": 51707313}
+
 WORKLOADS = {
     # 2-D, the paper's base-case contrast (1e6) at the 1024^2 size
     "smooth1024": dict(desc="2-D 5-point FV -div(k grad p)=f, 1024x1024 (1,048,576 unknowns); log10 k ~ U[-3,3] "
@@ -90,6 +97,31 @@ def run_gpu(P, opt, steps, warmup, time_small=False):
         prob.small_timing = prob.small_level_timing()
         prob.enable_kernel_timing(False)
     return prob, st, wall_ms, solve_ms, p
+
+
+def run_kernels_only(reps):
+    """The finest-level grid-wide kernels of the 1024^2 workload after one real solve, each
+    launched `reps` times back to back, and two plain copies of known size (64 MiB and
+    1 GiB of FP64) that calibrate the profiler's memory counters."""
+    import torch
+    from paper_math_9809043_amd import mscg
+    P = make_problem("smooth")
+    prob, st, _, _, _ = run_gpu(P, {}, 1, 0)
+    out = {}
+    for kid, name in ((mscg.KERNEL_SMOOTH_PRE, "smooth_pre"), (mscg.KERNEL_SMOOTH_POST, "smooth_post"),
+                      (mscg.KERNEL_SPMV, "spmv")):
+        us, nbytes = prob.time_kernel(kid, 0, reps=reps)
+        out[name] = {"avg_us": round(us, 3), "alg_bytes_per_launch": int(nbytes)}
+    for mib in (64, 1024):
+        n = mib * (1 << 20) // 8
+        a = torch.rand(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        out[f"copy_{mib}MiB"] = {"bytes_read": n * 8, "bytes_written": n * 8}
+    print(json.dumps({"kernels_only": out, "outer_iters": st.outer_iters}), flush=True)
 
 
 def run_scaling(sides, mgcg=True):
@@ -168,6 +200,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-scaling", action="store_true")
+    ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
+                    help="only launch the finest-level kernels and two calibration copies REPS times each "
+                         "(for memory-counter profiles); prints their timings")
     ap.add_argument("--scaling-sides", default="32,64,128,256,512,1024,2048,4096")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -179,6 +214,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     from paper_math_9809043_amd import mscg
+
+    if args.kernels_only > 0:
+        run_kernels_only(args.kernels_only)
+        return
 
     W = WORKLOADS[args.workload]
     P = make_problem(W["make"])
@@ -206,7 +245,8 @@ def main():
         roofline = {"bound": "alu", "kernel": "k_small_2x2<double>: inner PCG of the last inner level "
                     "with its dense coarsest solve, one workgroup", "achieved": round(achieved, 5),
                     "peak": round(PEAK_FP64_CU_TFLOPS, 5), "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_CU_TFLOPS, 4),
-                    "traffic": None, "avg_us": round(avg_us, 3), "launches": t["launches"],
+                    "traffic": PMC_TRAFFIC_SMOOTH1024["small_2x2"] if args.workload == "smooth1024" else None,
+                    "avg_us": round(avg_us, 3), "launches": t["launches"],
                     "iterations": t["iterations"], "alg_flops_per_launch": round(t["flops"] / max(t["launches"], 1), 1),
                     "share_of_step": round(t["total_ms"] / (wall_ms * args.steps), 4),
                     "peak_basis": "FP64 vector peak of one CU: 78.6 TFLOP/s / 256 CUs (a one-workgroup kernel "
@@ -217,16 +257,17 @@ def main():
               f"{roofline['share_of_step']:.2f} of the step", flush=True)
     # grid-wide kernels against HBM: the finest-level smoothers and SpMV
     hbm = []
-    kernels = [(mscg.KERNEL_SPMV, "k_spmv_dot<double> (finest level)")]
+    kernels = [(mscg.KERNEL_SPMV, "k_spmv_dot<double> (finest level)", "spmv")]
     if P.dim == 2:
-        kernels = [(mscg.KERNEL_SMOOTH_PRE, "k_smooth_tile<double, pre> (finest level, 9 half sweeps)"),
+        kernels = [(mscg.KERNEL_SMOOTH_PRE, "k_smooth_tile<double, pre> (finest level, 9 half sweeps)", "smooth_pre"),
                    (mscg.KERNEL_SMOOTH_POST, "k_smooth_tile<double, post> (finest level, prolongation + 9 half "
-                                             "sweeps)")] + kernels
-    for kid, name in kernels:
+                                             "sweeps)", "smooth_post")] + kernels
+    for kid, name, key in kernels:
         us, nbytes = prob.time_kernel(kid, 0, reps=50)
         gbs = nbytes / (us * 1e-6) / 1e9
         hbm.append({"kernel": name, "avg_us": round(us, 3), "alg_bytes_per_launch": int(nbytes),
-                    "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)})
+                    "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                    "traffic": PMC_TRAFFIC_SMOOTH1024[key] if args.workload == "smooth1024" else None})
     # whole solve against HBM: algorithmic bytes per level iteration and unknown
     # (fused smoothers, SpMV and CG vectors, FP64) times the executed iterations
     per_unk = 193.0 if P.dim == 2 else 216.0

@@ -27,6 +27,23 @@ namespace {
 
 constexpr int kHalo = 9;  // 2m + 1 for m = 4
 
+// Workgroups are handed to the chip's 8 XCDs (each with its own L2) in turn by
+// linear workgroup id.  Renumbering the tiles so that XCD x gets the x-th
+// contiguous run of tiles in row-major order keeps horizontally and
+// vertically adjacent tiles, whose halos overlap, on one L2.  The map is a
+// bijection of [0, T): the d-th workgroup sent to XCD x takes tile
+// x * (T / 8) + min(x, T % 8) + d.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int gx = gridDim.x;
+  const int T = gx * gridDim.y;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int x = lin % kXcds, d = lin / kXcds;
+  const int t = x * (T / kXcds) + min(x, T % kXcds) + d;
+  by = t / gx;
+  bx = t - by * gx;
+}
+
 template <typename R, bool POST, int TW, int TH, int BX, int BY>
 __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4 : 1) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                          const R* __restrict__ zin, const R* __restrict__ y,
@@ -39,7 +56,9 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
   static_assert(HW <= BX, "tile too wide for the thread layout");
   __shared__ R zc[2][MH][HW];              // [colour][region row][index within the colour]
   const int nx = L.nx, ny = L.ny;
-  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int x0 = tbx * TW, y0 = tby * TH;
   const int rx0 = max(x0 - kHalo, 0), ry0 = max(y0 - kHalo, 0);
   const int RW = min(x0 + TW + kHalo, nx) - rx0, RH = min(y0 + TH + kHalo, ny) - ry0;
   const int k = threadIdx.x % BX, ty = threadIdx.x / BX;
@@ -298,7 +317,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < BX * BY / kWave; ++w) t += wsum[w];
-      part[blockIdx.x + gridDim.x * blockIdx.y] = t;
+      part[tbx + gridDim.x * tby] = t;
     }
   }
 }
@@ -352,7 +371,9 @@ __global__ void __launch_bounds__(256) k_resid_restrict_tile(Lv<R> L, Xfer X, co
   __shared__ R tmp[kRegH][kCTx];
   __shared__ R wxt[kCTx][kFootMax], wyt[kCTy][kFootMax];  // footprint weights of the block's coarse columns, rows
   const int nx = L.nx, ny = L.ny, tid = threadIdx.x;
-  const int I0 = blockIdx.x * kCTx, J0 = blockIdx.y * kCTy;
+  int tbx, tby;
+  xcd_tile(tbx, tby);
+  const int I0 = tbx * kCTx, J0 = tby * kCTy;
   const int I1 = min(I0 + kCTx, X.cnx) - 1, J1 = min(J0 + kCTy, X.cny) - 1;
   int lox, hix, loy, hiy, t0, t1;
   ext_support(I0, X.sx, nx, X.interp, lox, t0);
