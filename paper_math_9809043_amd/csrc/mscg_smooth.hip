@@ -63,11 +63,12 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
   const int RW = min(x0 + TW + kHalo, nx) - rx0, RH = min(y0 + TH + kHalo, ny) - ry0;
   const int k = threadIdx.x % BX, ty = threadIdx.x / BX;
 
-  // Small tiles (latency-bound levels) and the pre-smoother issue every load
-  // before the first wait; the post-smoother on large tiles, which runs at
-  // its register limit, stages the coarse patch first (gate, patch, then the
-  // coefficients: three round trips, fewer live registers).
-  constexpr bool kEarly = !POST || TW * TH <= 196;
+  // Small tiles (latency-bound levels), the pre-smoother and tiles with at
+  // most two region rows per thread issue every load before the first wait;
+  // the post-smoother on the other large tiles, which runs at its register
+  // limit, stages the coarse patch first (gate, patch, then the coefficients:
+  // three round trips, fewer live registers).
+  constexpr bool kEarly = !POST || TW * TH <= 196 || BY >= 16;
   R cw[NR][2], ce[NR][2], cs[NR][2], cn[NR][2], dg[NR][2], rr[NR][2];
   if constexpr (kEarly) {
     // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
@@ -339,11 +340,13 @@ hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin,
 constexpr int kShapeTW[4] = {64, 110, 46, 14}, kShapeTH[4] = {32, 38, 14, 14};
 
 // Tile shapes: 0 = 64 x 32 (512 threads), 1 = 110 x 38 (512 threads, region
-// rows of exactly 128 cells), 2 = 46 x 14 (256 threads), 3 = 14 x 14 (256
-// threads).  Larger tiles re-read less halo but hold more registers per
-// thread, which caps the waves per CU; measured on MI355X (1024^2 and 256^2
-// levels), the small-register shapes win: 46 x 14 on the largest levels,
-// 14 x 14 below.
+// rows of exactly 128 cells), 2 = 46 x 14 (512 threads, two region rows per
+// thread), 3 = 14 x 14 (256 threads).  Larger tiles re-read less halo but
+// hold more registers per thread, which caps the waves per CU; measured on
+// MI355X (1024^2 and 256^2 levels), the small-register shapes win: 46 x 14
+// on the largest levels, 14 x 14 below.  Shape 2 with 256 threads (four
+// region rows per thread) spilled in the post-smoother and ran 27 / 48 us
+// per 1024^2 pre / post launch against 23 / 44 us with 512.
 int auto_shape(int nx, int ny) {
   const long long cells = (long long)nx * ny;
   return cells >= (1LL << 19) ? 2 : 3;
@@ -486,7 +489,7 @@ hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R
   switch (shape) {
     case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
     case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
-    case 2: return launch_tiles<R, 46, 14, 32, 8>(L, X, r, zin, y, zout, s, gate, part);
+    case 2: return launch_tiles<R, 46, 14, 32, 16>(L, X, r, zin, y, zout, s, gate, part);
     default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate, part);
   }
 }
