@@ -88,6 +88,14 @@ def lib():
         L.oracle_hierarchy_T.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, dp, ctypes.c_size_t, dp]
         L.oracle_hierarchy_T.restype = ctypes.c_int
+        L.oracle_prolong_add_dims.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
+        L.oracle_prolong_add_dims.restype = None
+        L.oracle_restrict_dims.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
+        L.oracle_restrict_dims.restype = None
+        L.oracle_set_frac_scale.argtypes = [ctypes.c_double]
+        L.oracle_set_frac_scale.restype = None
+        L.oracle_level_plan_frac.argtypes = [ctypes.c_int, ip, ctypes.c_double, ctypes.c_int, ctypes.c_int, ip]
+        L.oracle_level_plan_frac.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -144,7 +152,7 @@ def _axis_w(axis_weight):
 
 
 def solve_arrays(dim, n, kx, ky, kz, f, bc_type, bc_value, tol, length=(1.0, 1.0, 1.0), flvl=0.1,
-                 axis_weight=None, **opt) -> Result:
+                 axis_weight=None, frac_scale=0.0, **opt) -> Result:
     """Solve -div(K grad p) = f with the oracle's recursive multi-scale PCG.  axis_weight:
     per-axis permeability scale for the aspect-ratio-aware level plan (None: uniform plan)."""
     L = lib()
@@ -164,8 +172,12 @@ def solve_arrays(dim, n, kx, ky, kz, f, bc_type, bc_value, tol, length=(1.0, 1.0
     bcv = np.asarray(bc_value, dtype=np.float64)
     Ld = np.asarray(length, dtype=np.float64)
     fl = np.array([flvl])
-    L.oracle_solve(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), _d(f), bct, _d(bcv), float(tol), opt_p, _d(fl),
-                   _d(p), ctypes.byref(st), _d(aw))
+    L.oracle_set_frac_scale(float(frac_scale))
+    try:
+        L.oracle_solve(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), _d(f), bct, _d(bcv), float(tol), opt_p, _d(fl),
+                       _d(p), ctypes.byref(st), _d(aw))
+    finally:
+        L.oracle_set_frac_scale(0.0)
     nl = st.nlev
     return Result(p=p, status=st.status, outer_iters=st.outer_iters, nlev=nl,
                   level_n=[tuple(st.level_n[l]) for l in range(nl)],
@@ -180,11 +192,15 @@ def solve(problem, tol=None, **opt) -> Result:
                         problem.bc_value, problem.tol if tol is None else tol, length=problem.length, **opt)
 
 
-def level_plan(dim, n, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None, length=(1.0, 1.0, 1.0)):
+def level_plan(dim, n, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None, length=(1.0, 1.0, 1.0),
+               frac_scale=0.0):
     L = lib()
     dims = (ctypes.c_int * (3 * MAX_LEVELS))()
     npt, _a = _i(n)
-    if axis_weight is None:
+    if frac_scale > 0.0:
+        nl = L.oracle_level_plan_frac(dim, npt, float(frac_scale), min_side, max_levels,
+                                      ctypes.cast(dims, ctypes.POINTER(ctypes.c_int)))
+    elif axis_weight is None:
         nl = L.oracle_level_plan(dim, npt, scale, min_side, max_levels, ctypes.cast(dims, ctypes.POINTER(ctypes.c_int)))
     else:
         Ld = np.asarray(length, dtype=np.float64)
@@ -281,6 +297,26 @@ def restrict(dim, fd, s, rf, interp=LINEAR):
     return g
 
 
+def prolong_add_dims(dim, fd, cd, yc, xf, interp=LINEAR):
+    """xf + E yc between a fine grid fd and a coarser grid cd (factors need not be integers)."""
+    L = lib()
+    a, _a = _i((fd[0], fd[1], fd[2] if dim == 3 else 1))
+    b, _b = _i((cd[0], cd[1], cd[2] if dim == 3 else 1))
+    xf = np.array(xf, dtype=np.float64, copy=True)
+    L.oracle_prolong_add_dims(dim, a, b, int(interp), _d(_f64(yc)), _d(xf))
+    return xf
+
+
+def restrict_dims(dim, fd, cd, rf, interp=LINEAR):
+    """E^T rf from a fine grid fd to a coarser grid cd."""
+    L = lib()
+    a, _a = _i((fd[0], fd[1], fd[2] if dim == 3 else 1))
+    b, _b = _i((cd[0], cd[1], cd[2] if dim == 3 else 1))
+    g = np.zeros(cd[0] * cd[1] * (cd[2] if dim == 3 else 1))
+    L.oracle_restrict_dims(dim, a, b, int(interp), _d(_f64(rf)), _d(g))
+    return g
+
+
 def cholesky(A):
     L = lib()
     A = _f64(A)
@@ -297,7 +333,7 @@ def cholesky_solve(Lf, b):
     return x
 
 
-def precond(problem, r, eps2=0.0, flvl=0.1, axis_weight=None, **opt):
+def precond(problem, r, eps2=0.0, flvl=0.1, axis_weight=None, frac_scale=0.0, **opt):
     """z = M_0^-1 r on the problem's hierarchy (level-0 preconditioner of eq. 2.10)."""
     L = lib()
     aw = _axis_w(axis_weight)
@@ -310,19 +346,24 @@ def precond(problem, r, eps2=0.0, flvl=0.1, axis_weight=None, **opt):
     o, _c = _i(_opts(**opt))
     z = np.zeros(problem.N)
     Ld = np.asarray(problem.length, dtype=np.float64)
-    rc = L.oracle_precond(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), bct, o, float(flvl), float(eps2),
-                          _d(_f64(r)), _d(z), _d(aw))
+    L.oracle_set_frac_scale(float(frac_scale))
+    try:
+        rc = L.oracle_precond(dim, npt, _d(Ld), _d(kx), _d(ky), _d(kz), bct, o, float(flvl), float(eps2),
+                              _d(_f64(r)), _d(z), _d(aw))
+    finally:
+        L.oracle_set_frac_scale(0.0)
     if rc != 0:
         raise RuntimeError(f"oracle_precond failed: {rc}")
     return z
 
 
-def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None):
+def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight=None, frac_scale=0.0):
     """Per-level face arrays [(dims, tx, ty, tz), ...] of the problem's hierarchy."""
     L = lib()
     dim, n = problem.dim, problem.n
     aw = _axis_w(axis_weight)
-    plan = level_plan(dim, n, scale, min_side, max_levels, axis_weight=aw, length=problem.length)
+    plan = level_plan(dim, n, scale, min_side, max_levels, axis_weight=aw, length=problem.length,
+                      frac_scale=frac_scale)
     sizes = []
     total = 0
     for d in plan:
@@ -336,8 +377,12 @@ def hierarchy_T(problem, scale=4, min_side=8, max_levels=MAX_LEVELS, axis_weight
     bct, _b = _i(problem.bc_type)
     Ld = np.asarray(problem.length, dtype=np.float64)
     kz = _f64(problem.kz) if dim == 3 else None
-    nl = L.oracle_hierarchy_T(dim, npt, _d(Ld), _d(_f64(problem.kx)), _d(_f64(problem.ky)), _d(kz), bct, scale,
-                              min_side, max_levels, _d(out), out.size, _d(aw))
+    L.oracle_set_frac_scale(float(frac_scale))
+    try:
+        nl = L.oracle_hierarchy_T(dim, npt, _d(Ld), _d(_f64(problem.kx)), _d(_f64(problem.ky)), _d(kz), bct, scale,
+                                  min_side, max_levels, _d(out), out.size, _d(aw))
+    finally:
+        L.oracle_set_frac_scale(0.0)
     assert nl == len(plan), (nl, plan)
     res = []
     off = 0

@@ -96,6 +96,35 @@ int oracle_level_plan(int dim, const int n[3], int scale, int min_side, int max_
   return nl;
 }
 
+/* Plan with a factor that need not be an integer (Section 3: the scale
+ * factor between grids is not limited to an integer; the effective factor
+ * varies slightly so that every level has an integer dimension).  Each
+ * coarsened axis goes from d to round(d / scale) cells while every result is
+ * >= min_side and smaller than d.  g_frac_scale > 0 selects it for the
+ * solver entry points (set by oracle_set_frac_scale; 0 restores the integer
+ * plans). */
+static double g_frac_scale = 0.0;
+void oracle_set_frac_scale(double scale) { g_frac_scale = scale > 0.0 ? scale : 0.0; }
+
+int oracle_level_plan_frac(int dim, const int n[3], double scale, int min_side, int max_levels, int dims[][3]) {
+  int d[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+  int nl = 0;
+  if (max_levels > OR_MAX_LEVELS) max_levels = OR_MAX_LEVELS;
+  for (;;) {
+    dims[nl][0] = d[0]; dims[nl][1] = d[1]; dims[nl][2] = d[2];
+    nl++;
+    if (nl >= max_levels) break;
+    int c[3] = {d[0], d[1], d[2]}, ok = 1;
+    for (int a = 0; a < dim; ++a) {
+      c[a] = (int)floor(d[a] / scale + 0.5);
+      if (c[a] < min_side || c[a] >= d[a]) ok = 0;
+    }
+    if (!ok) break;
+    for (int a = 0; a < dim; ++a) d[a] = c[a];
+  }
+  return nl;
+}
+
 /* Aspect-ratio-aware plan (Section 5, anisotropic strip: coarsening aims at
  * cells of aspect ratio 1, so the finer direction is coarsened first, then
  * both).  The effective size of a cell along axis a is h_a / sqrt(w_a), with
@@ -195,25 +224,38 @@ void oracle_face_T(int dim, int nx, int ny, int nz, double hx, double hy, double
 /* ------------------------------------------------------------------------ */
 
 /* Overlap, in units of the fine spacing, of fine face i's span with coarse
- * face I's span, divided by the fine span's width. nf = number of fine cells
- * along the axis, s = factor, nc = nf / s. */
-static double face_overlap(int i, int I, int s, int nf, int nc) {
+ * face I's span, divided by the fine span's width (the fraction of the width
+ * in the overlap).  nf, nc = fine and coarse cells along the axis; the factor
+ * f = nf / nc need not be an integer (Section 3). */
+static double face_overlap(int i, int I, int nf, int nc) {
+  double f = (double)nf / nc;
   double a0 = i - 0.5, a1 = i + 0.5;
   if (i == 0) a0 = 0.0;
   if (i == nf) a1 = nf;
-  double b0 = (double)s * I - 0.5 * s, b1 = (double)s * I + 0.5 * s;
+  double b0 = f * I - 0.5 * f, b1 = f * I + 0.5 * f;
   if (I == 0) b0 = 0.0;
-  if (I == nc) b1 = (double)s * nc;
+  if (I == nc) b1 = nf;
   double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
   if (hi <= lo) return 0.0;
   return (hi - lo) / (a1 - a0);
 }
 
+/* Fraction of fine cell j (span [j, j+1]) inside coarse cell J (span
+ * [J f, (J+1) f], f = nf / nc): the fraction of the height in the overlap. */
+static double cell_overlap(int j, int J, int nf, int nc) {
+  double f = (double)nf / nc;
+  double b0 = f * J, b1 = J + 1 == nc ? (double)nf : f * (J + 1);
+  double lo = j > b0 ? j : b0, hi = j + 1 < b1 ? j + 1 : b1;
+  return hi > lo ? hi - lo : 0.0;
+}
+
 /* Generic coarsening of one face array along `axis` (0, 1, 2).  Fine face
  * array f has dims (fnx + (axis==0), fny + (axis==1), fnz + (axis==2)); the
- * coarse one c likewise with the coarse cell counts. */
-static void coarsen_axis(int axis, const int fd[3], const int s[3], const double *f, double *c) {
-  int cd[3] = {fd[0] / s[0], fd[1] / s[1], fd[2] / s[2]};
+ * coarse one c likewise with the coarse cell counts cd.  A fine face that
+ * only partly overlaps the coarse face is weighted by the fraction of the
+ * height in the overlap (parallel sum) and inversely by the fraction of the
+ * width (series sum), Section 3. */
+static void coarsen_axis(int axis, const int fd[3], const int cd[3], const double *f, double *c) {
   int fe[3] = {fd[0], fd[1], fd[2]}, ce[3] = {cd[0], cd[1], cd[2]};
   fe[axis] += 1; ce[axis] += 1;
   int a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
@@ -225,21 +267,33 @@ static void coarsen_axis(int axis, const int fd[3], const int s[3], const double
         double inv = 0.0;
         int blocked = 0;
         /* fine faces along the axis that can overlap coarse face I */
-        int ilo = s[axis] * I - s[axis], ihi = s[axis] * I + s[axis];
+        double fa = (double)fd[axis] / cd[axis];
+        int ilo = (int)floor(fa * (I - 1)), ihi = (int)ceil(fa * (I + 1));
         if (ilo < 0) ilo = 0;
         if (ihi > fd[axis]) ihi = fd[axis];
+        /* fine cells across the face that overlap the coarse cell */
+        double f1 = (double)fd[a1] / cd[a1], f2 = (double)fd[a2] / cd[a2];
+        int ulo = (int)floor(f1 * C[a1]), uhi = (int)ceil(f1 * (C[a1] + 1));
+        int vlo = (int)floor(f2 * C[a2]), vhi = (int)ceil(f2 * (C[a2] + 1));
+        if (uhi > fd[a1]) uhi = fd[a1];
+        if (vhi > fd[a2]) vhi = fd[a2];
         for (int i = ilo; i <= ihi; ++i) {
-          double alpha = face_overlap(i, I, s[axis], fd[axis], cd[axis]);
+          double alpha = face_overlap(i, I, fd[axis], cd[axis]);
           if (alpha == 0.0) continue;
           double par = 0.0; /* parallel sum over the fine faces inside the coarse face */
-          for (int u = 0; u < s[a1]; ++u)
-            for (int v = 0; v < s[a2]; ++v) {
+          for (int u = ulo; u < uhi; ++u) {
+            double bu = cell_overlap(u, C[a1], fd[a1], cd[a1]);
+            if (bu == 0.0) continue;
+            for (int v = vlo; v < vhi; ++v) {
+              double bv = cell_overlap(v, C[a2], fd[a2], cd[a2]);
+              if (bv == 0.0) continue;
               int F[3];
               F[axis] = i;
-              F[a1] = C[a1] * s[a1] + u;
-              F[a2] = C[a2] * s[a2] + v;
-              par += f[F[0] + (size_t)fe[0] * (F[1] + (size_t)fe[1] * F[2])];
+              F[a1] = u;
+              F[a2] = v;
+              par += bu * bv * f[F[0] + (size_t)fe[0] * (F[1] + (size_t)fe[1] * F[2])];
             }
+          }
           if (par == 0.0) { blocked = 1; break; }
           inv += alpha / par;
         }
@@ -247,13 +301,20 @@ static void coarsen_axis(int axis, const int fd[3], const int s[3], const double
       }
 }
 
+/* cd: coarse cell counts (fd / integer factors, or any coarser counts) */
+static void coarsen_T_dims(int dim, const int fd[3], const int cd[3], const double *tx, const double *ty,
+                           const double *tz, double *ctx, double *cty, double *ctz) {
+  int f3[3] = {fd[0], fd[1], dim == 3 ? fd[2] : 1};
+  int c3[3] = {cd[0], cd[1], dim == 3 ? cd[2] : 1};
+  coarsen_axis(0, f3, c3, tx, ctx);
+  coarsen_axis(1, f3, c3, ty, cty);
+  if (dim == 3) coarsen_axis(2, f3, c3, tz, ctz);
+}
+
 void oracle_coarsen_T(int dim, const int fd[3], const int s[3], const double *tx, const double *ty,
                       const double *tz, double *ctx, double *cty, double *ctz) {
-  int f3[3] = {fd[0], fd[1], dim == 3 ? fd[2] : 1};
-  int s3[3] = {s[0], s[1], dim == 3 ? s[2] : 1};
-  coarsen_axis(0, f3, s3, tx, ctx);
-  coarsen_axis(1, f3, s3, ty, cty);
-  if (dim == 3) coarsen_axis(2, f3, s3, tz, ctz);
+  int cd[3] = {fd[0] / s[0], fd[1] / s[1], dim == 3 ? fd[2] / s[2] : 1};
+  coarsen_T_dims(dim, fd, cd, tx, ty, tz, ctx, cty, ctz);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -353,16 +414,23 @@ static void smooth(const or_level *L, const double *r, double *x, int m) {
 /* R = E^T.                                                                  */
 /* ------------------------------------------------------------------------ */
 
-/* 1-D weights: fine cell i (of nf = s*nc) takes coarse cells I0, I1 with
- * weights w0, w1.  Linear (interp = 0): coarse coordinate xi = (i + 1/2)/s -
- * 1/2, clamped to [0, nc-1] (zero slope at the boundary).  Piecewise constant
- * (interp = 1, the alternative the paper reports to work nearly as well): the
- * coarse cell containing the fine cell. */
+/* 1-D weights: fine cell i (of nf) takes coarse cells I0, I1 (of nc) with
+ * weights w0, w1; f = nf / nc need not be an integer.  Linear (interp = 0):
+ * coarse coordinate xi = (i + 1/2)/f - 1/2, clamped to [0, nc-1] (zero slope
+ * at the boundary).  Piecewise constant (interp = 1, the alternative the
+ * paper reports to work nearly as well): the coarse cell containing the fine
+ * cell's centre. */
 static int g_interp = 0;
-static void interp1(int i, int s, int nc, int *I0, double *w0, int *I1, double *w1) {
-  if (s == 1) { *I0 = i; *w0 = 1.0; *I1 = i; *w1 = 0.0; return; }
-  if (g_interp == 1) { *I0 = i / s; *w0 = 1.0; *I1 = i / s; *w1 = 0.0; return; }
-  double xi = (i + 0.5) / s - 0.5;
+static void interp1(int i, int nf, int nc, int *I0, double *w0, int *I1, double *w1) {
+  if (nf == nc) { *I0 = i; *w0 = 1.0; *I1 = i; *w1 = 0.0; return; }
+  double f = (double)nf / nc;
+  if (g_interp == 1) {
+    int I = (int)floor((i + 0.5) / f);
+    if (I > nc - 1) I = nc - 1;
+    *I0 = I; *w0 = 1.0; *I1 = I; *w1 = 0.0;
+    return;
+  }
+  double xi = (i + 0.5) / f - 0.5;
   if (xi <= 0.0) { *I0 = 0; *w0 = 1.0; *I1 = 0; *w1 = 0.0; return; }
   if (xi >= nc - 1) { *I0 = nc - 1; *w0 = 1.0; *I1 = nc - 1; *w1 = 0.0; return; }
   int b = (int)floor(xi);
@@ -374,13 +442,13 @@ static void interp1(int i, int s, int nc, int *I0, double *w0, int *I1, double *
 static void prolong_add(const or_level *F, const or_level *C, const double *yc, double *xf) {
   for (int k = 0; k < F->nz; ++k) {
     int K[2]; double wk[2];
-    interp1(k, F->sz, C->nz, &K[0], &wk[0], &K[1], &wk[1]);
+    interp1(k, F->nz, C->nz, &K[0], &wk[0], &K[1], &wk[1]);
     for (int j = 0; j < F->ny; ++j) {
       int J[2]; double wj[2];
-      interp1(j, F->sy, C->ny, &J[0], &wj[0], &J[1], &wj[1]);
+      interp1(j, F->ny, C->ny, &J[0], &wj[0], &J[1], &wj[1]);
       for (int i = 0; i < F->nx; ++i) {
         int I[2]; double wi[2];
-        interp1(i, F->sx, C->nx, &I[0], &wi[0], &I[1], &wi[1]);
+        interp1(i, F->nx, C->nx, &I[0], &wi[0], &I[1], &wi[1]);
         double v = 0.0;
         for (int a = 0; a < 2; ++a)
           for (int b = 0; b < 2; ++b)
@@ -397,13 +465,13 @@ static void restrict_T(const or_level *F, const or_level *C, const double *rf, d
   memset(gc, 0, sizeof(double) * C->n);
   for (int k = 0; k < F->nz; ++k) {
     int K[2]; double wk[2];
-    interp1(k, F->sz, C->nz, &K[0], &wk[0], &K[1], &wk[1]);
+    interp1(k, F->nz, C->nz, &K[0], &wk[0], &K[1], &wk[1]);
     for (int j = 0; j < F->ny; ++j) {
       int J[2]; double wj[2];
-      interp1(j, F->sy, C->ny, &J[0], &wj[0], &J[1], &wj[1]);
+      interp1(j, F->ny, C->ny, &J[0], &wj[0], &J[1], &wj[1]);
       for (int i = 0; i < F->nx; ++i) {
         int I[2]; double wi[2];
-        interp1(i, F->sx, C->nx, &I[0], &wi[0], &I[1], &wi[1]);
+        interp1(i, F->nx, C->nx, &I[0], &wi[0], &I[1], &wi[1]);
         double v = rf[i + (size_t)F->nx * (j + (size_t)F->ny * k)];
         for (int a = 0; a < 2; ++a)
           for (int b = 0; b < 2; ++b)
@@ -578,8 +646,11 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
   int dims[OR_MAX_LEVELS][3];
   memset(P, 0, sizeof(*P));
   P->dim = dim;
-  P->nlev = axis_w ? oracle_level_plan_semi(dim, n, Ldom, axis_w, scale, min_side, max_levels, dims)
-                   : oracle_level_plan(dim, n, scale, min_side, max_levels, dims);
+  if (g_frac_scale > 0.0)
+    P->nlev = oracle_level_plan_frac(dim, n, g_frac_scale, min_side, max_levels, dims);
+  else
+    P->nlev = axis_w ? oracle_level_plan_semi(dim, n, Ldom, axis_w, scale, min_side, max_levels, dims)
+                     : oracle_level_plan(dim, n, scale, min_side, max_levels, dims);
   for (int l = 0; l < P->nlev; ++l) {
     or_level *L = &P->lev[l];
     L->nx = dims[l][0]; L->ny = dims[l][1]; L->nz = dims[l][2];
@@ -599,8 +670,8 @@ static int build_problem(or_problem *P, int dim, const int n[3], const double Ld
   oracle_face_T(dim, L0->nx, L0->ny, L0->nz, L0->hx, L0->hy, L0->hz, kx, ky, kz, bc_type, L0->tx, L0->ty, L0->tz);
   for (int l = 1; l < P->nlev; ++l) {
     or_level *F = &P->lev[l - 1], *C = &P->lev[l];
-    int fd[3] = {F->nx, F->ny, F->nz}, s[3] = {F->sx, F->sy, F->sz};
-    oracle_coarsen_T(dim, fd, s, F->tx, F->ty, F->tz, C->tx, C->ty, C->tz);
+    int fd[3] = {F->nx, F->ny, F->nz}, cd[3] = {C->nx, C->ny, C->nz};
+    coarsen_T_dims(dim, fd, cd, F->tx, F->ty, F->tz, C->tx, C->ty, C->tz);
   }
   or_level *LL = &P->lev[P->nlev - 1];
   if (!factor) return 0;
@@ -771,6 +842,26 @@ void oracle_restrict(int dim, const int fd[3], const int s[3], int interp, const
   F.nx = fd[0]; F.ny = fd[1]; F.nz = dim == 3 ? fd[2] : 1;
   F.sx = s[0]; F.sy = s[1]; F.sz = dim == 3 ? s[2] : 1;
   C.nx = F.nx / F.sx; C.ny = F.ny / F.sy; C.nz = F.nz / F.sz; C.n = C.nx * C.ny * C.nz;
+  restrict_T(&F, &C, rf, gc);
+}
+
+/* The same transfers between a fine grid fd and any coarser grid cd (the
+ * factors fd / cd need not be integers). */
+void oracle_prolong_add_dims(int dim, const int fd[3], const int cd[3], int interp, const double *yc, double *xf) {
+  or_level F, C;
+  memset(&F, 0, sizeof(F)); memset(&C, 0, sizeof(C));
+  F.nx = fd[0]; F.ny = fd[1]; F.nz = dim == 3 ? fd[2] : 1; F.n = F.nx * F.ny * F.nz;
+  C.nx = cd[0]; C.ny = cd[1]; C.nz = dim == 3 ? cd[2] : 1; C.n = C.nx * C.ny * C.nz;
+  g_interp = interp == 1 ? 1 : 0;
+  prolong_add(&F, &C, yc, xf);
+}
+
+void oracle_restrict_dims(int dim, const int fd[3], const int cd[3], int interp, const double *rf, double *gc) {
+  or_level F, C;
+  memset(&F, 0, sizeof(F)); memset(&C, 0, sizeof(C));
+  F.nx = fd[0]; F.ny = fd[1]; F.nz = dim == 3 ? fd[2] : 1; F.n = F.nx * F.ny * F.nz;
+  C.nx = cd[0]; C.ny = cd[1]; C.nz = dim == 3 ? cd[2] : 1; C.n = C.nx * C.ny * C.nz;
+  g_interp = interp == 1 ? 1 : 0;
   restrict_T(&F, &C, rf, gc);
 }
 

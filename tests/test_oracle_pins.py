@@ -743,3 +743,85 @@ def test_polynomial_iterations_grow_with_the_grid():
         assert r.status == 0
         its.append(r.outer_iters)
     assert its[1] > 1.6 * its[0] and its[2] > 1.6 * its[1]
+
+
+# ------------------------------------------------- non-integer scale factors (Section 3)
+
+def test_fractional_plan_reproduces_table_1_sizes():
+    # Table 1: a 1001^2 grid coarsened by a factor of about 4 gives 252^2, 63^2, 16^2, 4^2
+    assert oracle.level_plan(2, (1001, 1001, 1), min_side=4, frac_scale=3.98) == \
+        [(1001, 1001, 1), (252, 252, 1), (63, 63, 1), (16, 16, 1), (4, 4, 1)]
+
+
+def test_fractional_path_with_integer_factors_is_the_integer_method():
+    # with exact division the fractional overlaps, weights and plan reduce to the integer ones, bit for bit
+    P = problem_2d((64, 64), lo=-3, hi=3, seed=5)
+    a = oracle.solve(P, tol=1e-10)
+    b = oracle.solve(P, tol=1e-10, frac_scale=4.0)
+    assert a.level_n == b.level_n and a.outer_iters == b.outer_iters and np.array_equal(a.p, b.p)
+
+
+@pytest.mark.parametrize("n,fs", [((25, 25), 2.5), ((30, 20), 3.0), ((44, 44), 3.5)])
+def test_fractional_coarsening_of_uniform_K_is_the_coarse_discretisation(n, fs):
+    # uniform K on square cells: the coarse grid's own faces (1 inside, 2K on the Dirichlet faces,
+    # 0 on the no-flow faces), whatever fraction of a fine cell each coarse cell covers
+    nx, ny = n
+    P = problem_2d(n, seed=0)
+    P.kx = np.ones(nx * ny)
+    P.ky = P.kx.copy()
+    hier = oracle.hierarchy_T(P, min_side=2, max_levels=2, frac_scale=fs)
+    (d0, *_), (d1, tx, ty, _) = hier
+    cx, cy = d1[0], d1[1]
+    assert (cx, cy) == (int(np.floor(nx / fs + 0.5)), int(np.floor(ny / fs + 0.5)))
+    TX = tx.reshape(cy, cx + 1)
+    TY = ty.reshape(cy + 1, cx)
+    ratio_x = (1 / cy) / (1 / cx)  # coarse cell height / width (unit square)
+    ratio_y = 1 / ratio_x
+    assert np.allclose(TX[:, 1:-1], ratio_x, rtol=1e-12)
+    assert np.allclose(TX[:, [0, -1]], 2 * ratio_x, rtol=1e-12)
+    assert np.allclose(TY[1:-1, :], ratio_y, rtol=1e-12)
+    assert np.all(TY[[0, -1], :] == 0.0)
+
+
+@pytest.mark.parametrize("fd,cd", [((25, 1), (10, 1)), ((31, 7), (9, 3)), ((20, 12), (6, 5))])
+def test_fractional_transfers(fd, cd):
+    rng = np.random.default_rng(1)
+    nf, nc = fd[0] * fd[1], cd[0] * cd[1]
+    for interp in (oracle.LINEAR, oracle.CONSTANT):
+        # E 1 = 1
+        assert np.allclose(oracle.prolong_add_dims(2, fd, cd, np.ones(nc), np.zeros(nf), interp), 1.0, rtol=1e-14)
+        # <E u, v> = <u, R v>
+        u, v = rng.standard_normal(nc), rng.standard_normal(nf)
+        Eu = oracle.prolong_add_dims(2, fd, cd, u, np.zeros(nf), interp)
+        assert np.isclose(Eu @ v, u @ oracle.restrict_dims(2, fd, cd, v, interp), rtol=1e-12)
+    # linear E reproduces a linear field between the outermost coarse centres: coarse centre I
+    # sits at fine-index coordinate (I + 1/2) f - 1/2 with f = nf / nc
+    f = fd[0] / cd[0]
+    Xc = (np.arange(cd[0]) + 0.5) * f - 0.5
+    yc = np.tile(Xc, cd[1])
+    got = oracle.prolong_add_dims(2, fd, cd, yc, np.zeros(nf), oracle.LINEAR).reshape(fd[1], fd[0])
+    i = np.arange(fd[0])
+    inside = (i >= Xc[0]) & (i <= Xc[-1])
+    assert np.allclose(got[:, inside], i[inside], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,fs,interp", [((45, 45), 3.0, oracle.LINEAR), ((50, 30), 2.5, oracle.LINEAR),
+                                         ((63, 63), 3.98, oracle.CONSTANT)])
+def test_fractional_solve_matches_dense_solution(n, fs, interp):
+    P = problem_2d(n, lo=-2, hi=2, seed=12)
+    h = (1 / n[0], 1 / n[1], 1)
+    tx, ty, _ = oracle.face_T(2, P.n, h, P.kx, P.ky, None, P.bc_type)
+    A = dense_from_T(2, P.n, tx, ty)
+    x = np.linalg.solve(A, rhs(P, tx, ty))
+    r = oracle.solve(P, tol=1e-10, min_side=2, interp=interp, frac_scale=fs)
+    assert r.status == 0 and r.nlev >= 3 and r.rel_residual_true < 1e-10
+    assert np.linalg.norm(r.p - x) / np.linalg.norm(x) < 1e-8
+
+
+def test_fractional_preconditioner_is_symmetric_positive_definite():
+    # eq. 2.10 with a coarse grid that does not divide the fine one: W = E A_c^-1 R stays symmetric
+    P = problem_2d((20, 20), lo=-2, hi=2, seed=3)
+    N = P.N
+    got = np.stack([oracle.precond(P, e, m=2, min_side=2, max_levels=2, frac_scale=2.5) for e in np.eye(N)], axis=1)
+    assert np.allclose(got, got.T, atol=1e-12 * np.abs(got).max())
+    assert np.linalg.eigvalsh((got + got.T) / 2).min() > 0
