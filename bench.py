@@ -353,6 +353,23 @@ def main():
         extra["smooth1024_mgcg"] = dict({"workload": W["desc"] + "; Tatebe's multigrid preconditioner (eq. 2.9) "
                                          "in place of the inner PCGs"}, **res)
 
+    if not args.no_3d and args.workload == "smooth1024":
+        # a grid the integer factor cannot divide: 1001^2 coarsened by 3.98 per level, the level
+        # sizes of the paper's Table 1 (1001, 252, 63, 16, 4), with fractional overlaps
+        from paper_math_9809043_amd import synth
+        Pf = synth.smoothed_lognormal_2d(0, 1001, lo=-3.0, hi=3.0, tol=1e-10, name="smooth1001")
+        res = {}
+        for label, prec in (("fp64", mscg.FP64), ("mixed", mscg.MIXED)):
+            _, stf, wallf, solvef, _ = run_gpu(Pf, {"frac_scale": 3.98, "min_coarse_side": 4, "precision": prec}, 3, 1)
+            res[label] = {"value": round(Pf.N / (wallf * 1e-3), 1), "ms_per_step": round(wallf, 3),
+                          "outer_iters": stf.outer_iters, "level_n": [list(d) for d in stf.level_n],
+                          "level_iters": stf.level_iters, "rel_residual_true": stf.rel_residual_true}
+            print(f"[bench] smooth1001 factor 3.98 {label}: {wallf:.2f} ms/step (outer {stf.outer_iters}, levels "
+                  f"{stf.level_iters})", flush=True)
+        extra["smooth1001_frac3.98"] = dict({"workload": "2-D, 1001x1001, log10 k ~ U[-3,3] then 3x3 box mean, tol "
+                                             "1e-10; non-integer factor 3.98 (levels 1001, 252, 63, 16, 4), "
+                                             "host-driven grid-wide kernels on every level"}, **res)
+
     scaling = None
     if not args.no_scaling:
         scaling = run_scaling([int(v) for v in args.scaling_sides.split(",") if v])

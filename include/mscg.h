@@ -107,6 +107,12 @@ typedef struct {
                              MSCG_SPLIT_SGS (default) or MSCG_SPLIT_JACOBI */
   int cycle;              /* MSCG_CYCLE_RECURSIVE (default, eq. 2.10), MSCG_CYCLE_MGCG (eq. 2.9) or
                              MSCG_CYCLE_POLY (Section 2.1) */
+  double frac_scale;      /* 0 (default): integer factor `scale` with exact division.  > 1: a factor that
+                             need not be an integer (Section 3): each coarsened axis goes from d to
+                             round(d / frac_scale) cells while every result is >= min_coarse_side and
+                             < d, and the coarse graining weights partly overlapping fine faces by the
+                             fractions of the overlap.  Such hierarchies run host-driven with grid-wide
+                             kernels on every level; not combined with semi_coarsen */
 } mscg_options;
 
 typedef struct {

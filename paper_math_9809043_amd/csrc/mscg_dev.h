@@ -188,7 +188,48 @@ struct Xfer {
   int sx, sy, sz;       // factors fine -> coarse
   int cnx, cny, cnz;    // coarse dims
   int interp;
+  int frac;             // 1: factors fine / coarse need not be integers (sx.. unused)
 };
+
+// 1-D extension weights for a factor f = nf / nc that need not be an integer
+// (Section 3): linear interpolation at the coarse coordinate
+// xi = (i + 1/2) / f - 1/2 clamped to [0, nc - 1] (zero slope at the
+// boundary), or the coarse cell holding the fine cell's centre.  Computed in
+// FP64 and rounded once to R.
+template <typename R>
+__device__ __forceinline__ void ext_weights_frac(int i, int nf, int nc, int interp, int& I0, R& w0, int& I1, R& w1) {
+  I0 = I1 = i;
+  w0 = R(1);
+  w1 = R(0);
+  if (nf == nc) return;
+  const double f = (double)nf / nc;
+  if (interp == 1) {
+    int I = (int)floor((i + 0.5) / f);
+    I0 = I1 = I > nc - 1 ? nc - 1 : I;
+    return;
+  }
+  const double xi = (i + 0.5) / f - 0.5;
+  if (xi <= 0.0) { I0 = I1 = 0; return; }
+  if (xi >= nc - 1) { I0 = I1 = nc - 1; return; }
+  const int b = (int)floor(xi);
+  const double t = xi - b;
+  I0 = b;
+  I1 = b + 1;
+  w0 = R(1.0 - t);
+  w1 = R(t);
+}
+
+// weight of coarse cell I in fine cell i's extension, any factor
+template <typename R>
+__device__ __forceinline__ R ext_weight_of_frac(int i, int I, int nf, int nc, int interp) {
+  int I0, I1;
+  R w0, w1;
+  ext_weights_frac<R>(i, nf, nc, interp, I0, w0, I1, w1);
+  R w = R(0);
+  if (I0 == I) w += w0;
+  if (I1 == I && I1 != I0) w += w1;
+  return w;
+}
 
 // g_coarse = E^T (r - A x) on the fine level F for coarse cells [t0, nc) step nt.
 // x == nullptr means x = 0.

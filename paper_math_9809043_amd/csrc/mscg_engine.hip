@@ -93,6 +93,10 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
   if (o->semi_coarsen)
     for (int a = 0; a < g->dim; ++a)
       if (!(o->axis_weight[a] > 0.0)) return fail(MSCG_E_ARG, "axis_weight[%d] must be > 0", a);
+  const bool frac = o->frac_scale != 0.0;
+  if (frac && !(o->frac_scale > 1.0 && o->frac_scale <= 16.0))
+    return fail(MSCG_E_ARG, "frac_scale must be 0 or in (1, 16]");
+  if (frac && o->semi_coarsen) return fail(MSCG_E_ARG, "frac_scale cannot be combined with semi_coarsen");
   int nl = 0;
   for (;;) {
     LevelPlan& L = P->lv[nl];
@@ -100,6 +104,18 @@ int make_plan(const mscg_grid* g, const mscg_options* o, Plan* P) {
     L.n = d[0] * d[1] * d[2];
     ++nl;
     if (nl >= maxl) break;
+    if (frac) {
+      // a factor that need not be an integer: round(d / frac_scale) per axis
+      int c[3] = {d[0], d[1], d[2]};
+      bool ok = true;
+      for (int a = 0; a < g->dim; ++a) {
+        c[a] = (int)std::floor(d[a] / o->frac_scale + 0.5);
+        if (c[a] < o->min_coarse_side || c[a] >= d[a]) ok = false;
+      }
+      if (!ok) break;
+      for (int a = 0; a < g->dim; ++a) d[a] = c[a];
+      continue;
+    }
     if (o->semi_coarsen) {
       // aspect-ratio-aware: coarsen the axes whose effective cell size is within
       // sqrt(scale) of the smallest among those that can be coarsened
@@ -224,7 +240,7 @@ Lv<float> lv32(const mscg_problem* P, int k) {
 Xfer xfer(const mscg_problem* P, int k) {
   const LevelH& F = P->lev[k];
   const LevelH& C = P->lev[k + 1];
-  return Xfer{F.sx, F.sy, F.sz, C.nx, C.ny, C.nz, P->o.interp};
+  return Xfer{F.sx, F.sy, F.sz, C.nx, C.ny, C.nz, P->o.interp, P->o.frac_scale != 0.0 ? 1 : 0};
 }
 
 double level_tol(const mscg_problem* P, int k) {
@@ -672,6 +688,7 @@ void mscg_default_options(mscg_options* o) {
   o->axis_weight[0] = o->axis_weight[1] = o->axis_weight[2] = 1.0;
   o->splitting = MSCG_SPLIT_SGS;
   o->cycle = MSCG_CYCLE_RECURSIVE;
+  o->frac_scale = 0.0;
 }
 
 const char* mscg_last_error(void) { return g_err.c_str(); }
@@ -734,8 +751,9 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   if (rc) { mscg_destroy_problem(P); return rc; }
   const int sn = small_n();
   P->ks = P->nlev;  // no small level
-  // the one-workgroup solvers smooth by red-black SGS only, and run an inner PCG
-  if (P->o.splitting == MSCG_SPLIT_SGS && P->o.cycle == MSCG_CYCLE_RECURSIVE)
+  // the one-workgroup solvers smooth by red-black SGS only, run an inner PCG
+  // and use integer factors
+  if (P->o.splitting == MSCG_SPLIT_SGS && P->o.cycle == MSCG_CYCLE_RECURSIVE && P->o.frac_scale == 0.0)
     for (int l = 1; l < P->nlev - 1; ++l)
       if (P->lev[l].n <= sn) { P->ks = l; break; }
   for (int l = 0; l < P->nlev; ++l) {
@@ -754,7 +772,8 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   P->ready = false;
   {
     const char* e = getenv("MSCG_UNTILED");
-    P->tiled = !(e && e[0] == '1');
+    // the tiled kernels' transfers assume integer factors
+    P->tiled = !(e && e[0] == '1') && P->o.frac_scale == 0.0;
     const char* fd = getenv("MSCG_FUSED_DOT");
     P->fuse_dot = !(fd && fd[0] == '0');
     const char* ff = getenv("MSCG_FUSED_FINISH");
@@ -821,6 +840,7 @@ int mscg_set_permeability(mscg_problem* P, const double* kx, const double* ky, c
     for (int ax = 0; ax < P->g.dim; ++ax) {
       CoarsenArgs ca{};
       ca.axis = ax;
+      ca.frac = P->o.frac_scale != 0.0 ? 1 : 0;
       ca.fd[0] = F.nx; ca.fd[1] = F.ny; ca.fd[2] = F.nz;
       ca.cd[0] = C.nx; ca.cd[1] = C.ny; ca.cd[2] = C.nz;
       ca.s[0] = F.sx; ca.s[1] = F.sy; ca.s[2] = F.sz;
@@ -1050,6 +1070,7 @@ int mscg_restrict_residual(mscg_problem* P, int level, const double* r, const do
   if (!P) return fail(MSCG_E_ARG, "problem is NULL");
   if (level < 0 || level + 1 >= P->nlev) return fail(MSCG_E_ARG, "level must have a coarser level");
   if (!P->ready) return fail(MSCG_E_STATE, "permeability not set");
+  if (P->o.frac_scale != 0.0) return fail(MSCG_E_ARG, "not available on hierarchies with non-integer factors");
   HIP_TRY(launch_restrict<double>(lv64(P, level), xfer(P, level), r, x, g, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MSCG_OK;
@@ -1120,6 +1141,8 @@ int mscg_time_kernel(mscg_problem* P, int kernel, int level, int reps, double* a
   if ((kernel == MSCG_KERNEL_RESTRICT || kernel == MSCG_KERNEL_PROLONG || kernel == MSCG_KERNEL_SMOOTH_PRE ||
        kernel == MSCG_KERNEL_SMOOTH_POST) && level + 1 >= P->nlev)
     return fail(MSCG_E_ARG, "transfer and smoothing kernels need a coarser level");
+  if (P->o.frac_scale != 0.0 && (kernel == MSCG_KERNEL_RESTRICT || kernel == MSCG_KERNEL_SMOOTH_POST))
+    return fail(MSCG_E_ARG, "kernel not timed on hierarchies with non-integer factors");
   if ((kernel == MSCG_KERNEL_SMOOTH_PRE || kernel == MSCG_KERNEL_SMOOTH_POST) &&
       !smooth_tile_supported(P->lev[level].nz, P->g.dim == 3, P->o.smooth_steps))
     return fail(MSCG_E_ARG, "level %d has no tiled smoother", level);

@@ -43,6 +43,7 @@ struct FaceTArgs {
 
 struct CoarsenArgs {
   int axis;
+  int frac;  // 1: the factors fd / cd need not be integers (s unused)
   int fd[3], cd[3], s[3];
   const double* f;
   double* c;

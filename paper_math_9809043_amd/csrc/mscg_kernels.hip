@@ -141,6 +141,131 @@ __global__ void k_coarsen_axis(CoarsenArgs a) {
   a.c[t] = blocked ? 0.0 : 1.0 / inv;
 }
 
+// The same coarse graining for factors that need not be integers (Section 3):
+// a fine face that only partly overlaps the coarse face counts with the
+// fraction of the height in the overlap in the parallel sum and inversely
+// with the fraction of the width in the series sum.
+__device__ __forceinline__ double frac_face_overlap(int i, int I, int nf, int nc) {
+  const double f = (double)nf / nc;
+  const double a0 = i == 0 ? 0.0 : i - 0.5, a1 = i == nf ? (double)nf : i + 0.5;
+  const double b0 = I == 0 ? 0.0 : f * I - 0.5 * f, b1 = I == nc ? (double)nf : f * I + 0.5 * f;
+  const double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+  return hi > lo ? (hi - lo) / (a1 - a0) : 0.0;
+}
+
+__device__ __forceinline__ double frac_cell_overlap(int j, int J, int nf, int nc) {
+  const double f = (double)nf / nc;
+  const double b0 = f * J, b1 = J + 1 == nc ? (double)nf : f * (J + 1);
+  const double lo = j > b0 ? (double)j : b0, hi = j + 1 < b1 ? (double)(j + 1) : b1;
+  return hi > lo ? hi - lo : 0.0;
+}
+
+__global__ void k_coarsen_frac(CoarsenArgs a) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int ce[3] = {a.cd[0], a.cd[1], a.cd[2]};
+  int fe[3] = {a.fd[0], a.fd[1], a.fd[2]};
+  ce[a.axis] += 1;
+  fe[a.axis] += 1;
+  const long long total = (long long)ce[0] * ce[1] * ce[2];
+  if (t >= total) return;
+  int C[3];
+  C[0] = (int)(t % ce[0]);
+  C[1] = (int)((t / ce[0]) % ce[1]);
+  C[2] = (int)(t / ((long long)ce[0] * ce[1]));
+  const int ax = a.axis, a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+  const int I = C[ax];
+  const double fa = (double)a.fd[ax] / a.cd[ax];
+  int lo = (int)floor(fa * (I - 1)), hi = (int)ceil(fa * (I + 1));
+  if (lo < 0) lo = 0;
+  if (hi > a.fd[ax]) hi = a.fd[ax];
+  const double f1 = (double)a.fd[a1] / a.cd[a1], f2 = (double)a.fd[a2] / a.cd[a2];
+  const int ulo = (int)floor(f1 * C[a1]), vlo = (int)floor(f2 * C[a2]);
+  const int uhi = min((int)ceil(f1 * (C[a1] + 1)), a.fd[a1]), vhi = min((int)ceil(f2 * (C[a2] + 1)), a.fd[a2]);
+  double inv = 0.0;
+  bool blocked = false;
+  for (int i = lo; i <= hi && !blocked; ++i) {
+    const double alpha = frac_face_overlap(i, I, a.fd[ax], a.cd[ax]);
+    if (alpha == 0.0) continue;
+    double par = 0.0;
+    for (int u = ulo; u < uhi; ++u) {
+      const double bu = frac_cell_overlap(u, C[a1], a.fd[a1], a.cd[a1]);
+      if (bu == 0.0) continue;
+      for (int v = vlo; v < vhi; ++v) {
+        const double bv = frac_cell_overlap(v, C[a2], a.fd[a2], a.cd[a2]);
+        if (bv == 0.0) continue;
+        int F[3];
+        F[ax] = i;
+        F[a1] = u;
+        F[a2] = v;
+        par += bu * bv * a.f[F[0] + (long long)fe[0] * (F[1] + (long long)fe[1] * F[2])];
+      }
+    }
+    if (par == 0.0) blocked = true;
+    else inv += alpha / par;
+  }
+  a.c[t] = blocked ? 0.0 : 1.0 / inv;
+}
+
+// x_fine += E y for factors that need not be integers: one thread per fine cell
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_prolong_frac(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < F.n; c += gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, F.nx, F.ny, i, j, k);
+    int I[2], J[2], K[2];
+    R wi[2], wj[2], wk[2];
+    ext_weights_frac<R>(i, F.nx, X.cnx, X.interp, I[0], wi[0], I[1], wi[1]);
+    ext_weights_frac<R>(j, F.ny, X.cny, X.interp, J[0], wj[0], J[1], wj[1]);
+    ext_weights_frac<R>(k, F.nz, X.cnz, X.interp, K[0], wk[0], K[1], wk[1]);
+    R v = R(0);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 2; ++e) {
+          const R w = wk[a] * wj[b] * wi[e];
+          if (w != R(0)) v += w * y[I[e] + X.cnx * (J[b] + X.cny * K[a])];
+        }
+    x[c] += v;
+  }
+}
+
+// g = E^T res for factors that need not be integers: one thread per coarse
+// cell gathers the fine cells whose extension touches it
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_restrict_frac(Lv<R> F, Xfer X, const R* __restrict__ res, R* __restrict__ g,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int nc = X.cnx * X.cny * X.cnz;
+  auto range = [](int I, int nf, int ncs, int& lo, int& hi) {
+    if (nf == ncs) { lo = hi = I; return; }
+    const double f = (double)nf / ncs;
+    lo = max((int)floor((I - 1) * f) - 1, 0);
+    hi = min((int)ceil((I + 2) * f) + 1, nf - 1);
+  };
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const int I = c % X.cnx, J = (c / X.cnx) % X.cny, K = c / (X.cnx * X.cny);
+    int ilo, ihi, jlo, jhi, klo, khi;
+    range(I, F.nx, X.cnx, ilo, ihi);
+    range(J, F.ny, X.cny, jlo, jhi);
+    range(K, F.nz, X.cnz, klo, khi);
+    R acc = R(0);
+    for (int k = klo; k <= khi; ++k) {
+      const R wk = ext_weight_of_frac<R>(k, K, F.nz, X.cnz, X.interp);
+      if (wk == R(0)) continue;
+      for (int j = jlo; j <= jhi; ++j) {
+        const R wj = ext_weight_of_frac<R>(j, J, F.ny, X.cny, X.interp);
+        if (wj == R(0)) continue;
+        for (int i = ilo; i <= ihi; ++i) {
+          const R wi = ext_weight_of_frac<R>(i, I, F.nx, X.cnx, X.interp);
+          if (wi != R(0)) acc += wk * wj * wi * res[i + F.nx * (j + F.ny * k)];
+        }
+      }
+    }
+    g[c] = acc;
+  }
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -1150,7 +1275,10 @@ hipError_t launch_coarsen(const CoarsenArgs& a, hipStream_t s) {
   int ce[3] = {a.cd[0], a.cd[1], a.cd[2]};
   ce[a.axis] += 1;
   const long long tot = (long long)ce[0] * ce[1] * ce[2];
-  hipLaunchKernelGGL(k_coarsen_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  if (a.frac)
+    hipLaunchKernelGGL(k_coarsen_frac, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_coarsen_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1310,6 +1438,7 @@ hipError_t launch_mjac_step(const Lv<R>& L, const R* r, const R* xin, R* xout, i
 
 template <typename R>
 hipError_t launch_restrict(const Lv<R>& F, const Xfer& X, const R* r, const R* x, R* g, hipStream_t s) {
+  if (X.frac) return hipErrorNotSupported;  // the fractional path restricts a stored residual
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
   hipLaunchKernelGGL(k_restrict<R>, dim3(grid_for(nc, 1 << 20)), dim3(kBlock), 0, s, F, X, r, x, g);
   return hipGetLastError();
@@ -1320,6 +1449,11 @@ hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, c
                                     hipStream_t s, const int* gate) {
   const long long nc = (long long)X.cnx * X.cny * X.cnz;
   hipLaunchKernelGGL(k_residual_nodot<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, r, x, tmp, gate);
+  if (X.frac) {
+    hipLaunchKernelGGL(k_restrict_frac<R>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, F, X, (const R*)tmp, g,
+                       gate);
+    return hipGetLastError();
+  }
   // one thread per coarse cell; small coarse grids use 64-thread blocks to spread over more CUs
   if (nc < 65536)
     hipLaunchKernelGGL(k_restrict_stored<R>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, F, X, (const R*)tmp, g,
@@ -1332,7 +1466,10 @@ hipError_t launch_residual_restrict(const Lv<R>& F, const Xfer& X, const R* r, c
 
 template <typename R>
 hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipStream_t s, const int* gate) {
-  hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
+  if (X.frac)
+    hipLaunchKernelGGL(k_prolong_frac<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
+  else
+    hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
   return hipGetLastError();
 }
 

@@ -496,7 +496,7 @@ hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R
 
 bool resid_restrict_tile_supported(const Lv<double>& L, const Xfer& X) {
   auto ok = [&](int f) { return f >= 1 && f <= 4; };
-  return !L.tz && L.nz == 1 && X.cnz == 1 && ok(X.sx) && ok(X.sy);
+  return !X.frac && !L.tz && L.nz == 1 && X.cnz == 1 && ok(X.sx) && ok(X.sy);
 }
 
 template <typename R>

@@ -42,7 +42,8 @@ class _Options(ctypes.Structure):
                 ("level_factor", ctypes.c_double), ("min_coarse_side", ctypes.c_int), ("max_levels", ctypes.c_int),
                 ("max_outer_iters", ctypes.c_int), ("max_inner_iters", ctypes.c_int), ("interp", ctypes.c_int),
                 ("flexible", ctypes.c_int), ("inner_rel_floor", ctypes.c_double), ("semi_coarsen", ctypes.c_int),
-                ("axis_weight", ctypes.c_double * 3), ("splitting", ctypes.c_int), ("cycle", ctypes.c_int)]
+                ("axis_weight", ctypes.c_double * 3), ("splitting", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("frac_scale", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -169,6 +170,7 @@ class Options:
     axis_weight: tuple = (1.0, 1.0, 1.0)
     splitting: int = 0  # SPLIT_SGS or SPLIT_JACOBI
     cycle: int = 0  # CYCLE_RECURSIVE (eq. 2.10), CYCLE_MGCG (eq. 2.9) or CYCLE_POLY (Section 2.1)
+    frac_scale: float = 0.0  # > 1: coarsening factor that need not be an integer (Section 3)
 
     def _c(self) -> _Options:
         o = _Options()

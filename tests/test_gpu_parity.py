@@ -570,3 +570,50 @@ def test_polynomial_parity(name, make, opt):
         # FP64 follows the oracle's iteration to rounding; the FP32 preconditioner may move the
         # count of this slowly converging iteration a little further
         assert abs(st.outer_iters - ref.outer_iters) <= (2 if prec == mscg.FP64 else max(2, ref.outer_iters // 10))
+
+
+# ------------------------------------------- non-integer scale factors (Section 3)
+
+FRAC_CASES = [
+    ("smooth1001_s3.98", lambda: synth.smoothed_lognormal_2d(2, 1001, lo=-3, hi=3), 3.98, {"min_coarse_side": 4}),
+    ("rect250x170_s2.5", lambda: synth.smoothed_lognormal_2d(3, 250, 170, lo=-3, hi=3), 2.5, {}),
+    ("small45_s3_const", lambda: synth.smoothed_lognormal_2d(4, 45, lo=-2, hi=2), 3.0,
+     {"min_coarse_side": 2, "interp": 1}),
+    ("smooth256_s4", lambda: synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), 4.0, {}),
+    ("layered30_s2.5_const", lambda: synth.layered_3d(2, 30, n_layers=6), 2.5, {"min_coarse_side": 4, "interp": 1}),
+]
+
+
+@pytest.mark.parametrize("name,make,fs,opt", FRAC_CASES, ids=[c[0] for c in FRAC_CASES])
+def test_fractional_scale_parity(name, make, fs, opt):
+    """Hierarchies whose factors need not be integers (coarse graining with
+    partial overlaps, fractional extension weights): the level sizes, full
+    solves in FP64 and mixed against the oracle's, and eq. 2.9's
+    preconditioner over the whole hierarchy to rounding."""
+    from paper_math_9809043_amd import mscg
+    case(f"fractional scale {name}")
+    torch = _torch()
+    P = make()
+    gopt = dict(opt, frac_scale=fs)
+    oopt = dict(oracle_opts(opt), frac_scale=fs)
+    ref = oracle.solve(P, **oopt)
+    assert ref.status == 0 and ref.nlev >= 3
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec, **gopt)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: levels {st.level_n} outer {st.outer_iters} (oracle {ref.outer_iters}) iters "
+              f"{st.level_iters} (oracle {ref.level_iters}) res {st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert [tuple(d) for d in st.level_n] == [tuple(d) for d in ref.level_n]
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
+    # Tatebe's preconditioner over the whole hierarchy has no inner PCG, so M^-1 r differs from
+    # the oracle's by rounding only: every level's fractional transfers and coarse graining
+    prob = make_problem(P, cycle=mscg.CYCLE_MGCG, **gopt)
+    r = np.random.default_rng(9).standard_normal(P.N)
+    z = torch.empty(P.N, dtype=torch.float64, device="cuda")
+    prob.apply_preconditioner(dev_tensor(r), z, 0.0)
+    zo = oracle.precond(P, r, cycle=oracle.MGCG, **oopt)
+    err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"  eq. 2.9 preconditioner rel diff {err:.2e}", flush=True)
+    assert err < 1e-10
