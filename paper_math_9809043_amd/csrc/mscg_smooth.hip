@@ -340,13 +340,15 @@ hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin,
 constexpr int kShapeTW[4] = {64, 110, 46, 14}, kShapeTH[4] = {32, 38, 14, 14};
 
 // Tile shapes: 0 = 64 x 32 (512 threads), 1 = 110 x 38 (512 threads, region
-// rows of exactly 128 cells), 2 = 46 x 14 (512 threads, two region rows per
-// thread), 3 = 14 x 14 (256 threads).  Larger tiles re-read less halo but
-// hold more registers per thread, which caps the waves per CU; measured on
-// MI355X (1024^2 and 256^2 levels), the small-register shapes win: 46 x 14
-// on the largest levels, 14 x 14 below.  Shape 2 with 256 threads (four
-// region rows per thread) spilled in the post-smoother and ran 27 / 48 us
-// per 1024^2 pre / post launch against 23 / 44 us with 512.
+// rows of exactly 128 cells), 2 = 46 x 14 (1024 threads for the pre-smoother,
+// 512 for the post-smoother), 3 = 14 x 14 (512 threads, one region row per
+// thread).  Larger tiles re-read less halo but hold more registers per
+// thread, which caps the waves per CU; measured on MI355X (1024^2 and 256^2
+// levels), the small-register shapes win: 46 x 14 on the largest levels,
+// 14 x 14 below.  Per 1024^2 launch, shape 2 ran pre / post in 27 / 48 us
+// with 256 threads (four region rows per thread; the post-smoother spilled),
+// 23 / 44 us with 512 and 20 / 59 us with 1024.  Shape 3 on a 256^2 level:
+// 7.3 / 11.4 us with 256 threads, 5.2 / 9.2 us with 512.
 int auto_shape(int nx, int ny) {
   const long long cells = (long long)nx * ny;
   return cells >= (1LL << 19) ? 2 : 3;
@@ -489,8 +491,10 @@ hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R
   switch (shape) {
     case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
     case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
-    case 2: return launch_tiles<R, 46, 14, 32, 16>(L, X, r, zin, y, zout, s, gate, part);
-    default: return launch_tiles<R, 14, 14, 16, 16>(L, X, r, zin, y, zout, s, gate, part);
+    case 2:  // one region row per thread for the pre-smoother, two for the post-smoother
+      return X ? launch_tiles<R, 46, 14, 32, 16>(L, X, r, zin, y, zout, s, gate, part)
+               : launch_tiles<R, 46, 14, 32, 32>(L, X, r, zin, y, zout, s, gate, part);
+    default: return launch_tiles<R, 14, 14, 16, 32>(L, X, r, zin, y, zout, s, gate, part);
   }
 }
 
