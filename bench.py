@@ -26,7 +26,7 @@ PEAK_FP64_CU_TFLOPS = 78.6 / 256  # MI355X FP64 vector peak per CU (256 CUs)
 # copy of known size), WRITE_SIZE by 1.0.  Taken for the kernels as they stand; a kernel change
 # invalidates its figure.
 PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 361258, "smooth_pre": 36879673, "smooth_post": 47134059,
-                          "spmv": 51707313}
+                          "spmv": 33818263}
 
 WORKLOADS = {
     # 2-D, the paper's base-case contrast (1e6) at the 1024^2 size

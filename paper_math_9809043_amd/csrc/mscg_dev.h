@@ -94,6 +94,18 @@ __device__ __forceinline__ void cell_ijk(int c, int nx, int ny, int& i, int& j, 
   k = t / ny;
 }
 
+// The workgroup's contiguous run of cells [c0, c1) for a grid-wide stencil
+// kernel: workgroups go to the 8 XCDs in turn, so they are renumbered to give
+// each XCD a contiguous stretch of rows and keep a row's neighbour rows on its L2.
+__device__ __forceinline__ void block_cells(int n, int& c0, int& c1) {
+  const int nb = gridDim.x, lin = blockIdx.x;
+  const int x = lin % 8, d = lin / 8;
+  const int b = x * (nb / 8) + min(x, nb % 8) + d;
+  const int per = (n + nb - 1) / nb;
+  c0 = min(n, b * per);
+  c1 = min(n, c0 + per);
+}
+
 // y = A x over cells [t0, n) step nt; returns the thread's share of x . y.
 template <typename R, typename A>
 __device__ __forceinline__ A spmv_range(const Lv<R>& L, const R* __restrict__ x, R* __restrict__ y, int t0, int nt) {

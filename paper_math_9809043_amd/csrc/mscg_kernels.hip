@@ -578,7 +578,18 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(Lv<R> L, const R* __restrict__ x, R* __restrict__ y,
                                                       double* __restrict__ part) {
   __shared__ double sm[kBlock / kWave];
-  const double acc = spmv_range<R, double>(L, x, y, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  int c0, c1;
+  block_cells(L.n, c0, c1);
+  double acc = 0.0;
+  for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    int i, j, k;
+    cell_ijk(c, L.nx, L.ny, i, j, k);
+    R d, o;
+    stencil_at(L, x, i, j, k, c, d, o);
+    const R v = d * x[c] - o;
+    y[c] = v;
+    acc += double(x[c]) * double(v);
+  }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0 && part) part[blockIdx.x] = s;
 }
@@ -839,7 +850,9 @@ __device__ __forceinline__ double pspmv_range(const Lv<R>& L, const R* __restric
   auto pv = [&](int c) { return first ? z[c] : z[c] + beta * pold[c]; };
   double acc = 0.0;
   const int nx = L.nx, ny = L.ny;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+  int c0, c1;
+  block_cells(L.n, c0, c1);
+  for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     int i, j, k;
     cell_ijk(c, nx, ny, i, j, k);
     const int fx = i + (nx + 1) * (j + ny * k);
