@@ -94,13 +94,18 @@ __device__ __forceinline__ void cell_ijk(int c, int nx, int ny, int& i, int& j, 
   k = t / ny;
 }
 
-// The workgroup's contiguous run of cells [c0, c1) for a grid-wide stencil
-// kernel: workgroups go to the 8 XCDs in turn, so they are renumbered to give
-// each XCD a contiguous stretch of rows and keep a row's neighbour rows on its L2.
-__device__ __forceinline__ void block_cells(int n, int& c0, int& c1) {
+// Workgroups go to the 8 XCDs in turn.  xcd_block() renumbers them (a
+// bijection of [0, gridDim.x)) so that XCD x holds the x-th contiguous run of
+// workgroup numbers; block_cells() gives the workgroup its contiguous run of
+// cells [c0, c1).  A row's neighbour rows then stay on the same L2.
+__device__ __forceinline__ int xcd_block() {
   const int nb = gridDim.x, lin = blockIdx.x;
   const int x = lin % 8, d = lin / 8;
-  const int b = x * (nb / 8) + min(x, nb % 8) + d;
+  return x * (nb / 8) + min(x, nb % 8) + d;
+}
+
+__device__ __forceinline__ void block_cells(int n, int& c0, int& c1) {
+  const int nb = gridDim.x, b = xcd_block();
   const int per = (n + nb - 1) / nb;
   c0 = min(n, b * per);
   c1 = min(n, c0 + per);

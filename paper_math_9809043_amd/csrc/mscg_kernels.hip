@@ -618,7 +618,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_residual_nodot(Lv<R> L, const R* __restrict__ b, const R* __restrict__ x,
                                                             R* __restrict__ res, const int* __restrict__ gate) {
   if (gate && *gate) return;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+  for (int c = xcd_block() * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
     int i, j, k;
     cell_ijk(c, L.nx, L.ny, i, j, k);
     R d, o;
@@ -673,7 +673,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_mjac_step(Lv<R> L, const R* __restrict__ r, const R* __restrict__ xin,
                                                        R* __restrict__ xout, int first, const int* __restrict__ gate) {
   if (gate && *gate) return;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
+  for (int c = xcd_block() * blockDim.x + threadIdx.x; c < L.n; c += gridDim.x * blockDim.x) {
     int i, j, k;
     cell_ijk(c, L.nx, L.ny, i, j, k);
     R d, o;
@@ -691,7 +691,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gs_half(Lv<R> L, const R* __restrict__ r, R* __restrict__ x, int colour,
                                                      int first, const int* __restrict__ gate) {
   if (gate && *gate) return;
-  gs_half_range(L, r, x, colour, first != 0, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  gs_half_range(L, r, x, colour, first != 0, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 template <typename R>
