@@ -617,3 +617,33 @@ def test_fractional_scale_parity(name, make, fs, opt):
     err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
     print(f"  eq. 2.9 preconditioner rel diff {err:.2e}", flush=True)
     assert err < 1e-10
+
+
+def test_batch_matches_single_for_every_cycle_and_fractional_plans():
+    """mscg_solve_batch with problems of different cycles, splittings and level
+    plans in one call: each result is bitwise the one it gets alone."""
+    from paper_math_9809043_amd import mscg
+    case("batch of mixed cycles and plans")
+    torch = _torch()
+    jobs = [
+        (synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3), {"cycle": mscg.CYCLE_MGCG}),
+        (synth.smoothed_lognormal_2d(2, 64, lo=-2, hi=2), {"cycle": mscg.CYCLE_POLY, "max_outer_iters": 2000}),
+        (synth.smoothed_lognormal_2d(3, 250, 170, lo=-3, hi=3), {"frac_scale": 2.5}),
+        (synth.smoothed_lognormal_2d(4, 128, lo=-3, hi=3), {}),
+        (synth.smoothed_lognormal_2d(5, 128, lo=-3, hi=3), {"precision": mscg.MIXED, "cycle": mscg.CYCLE_MGCG}),
+    ]
+    probs, fs, ps, singles = [], [], [], []
+    for P, opt in jobs:
+        prob = make_problem(P, **opt)
+        probs.append(prob)
+        fs.append(dev_tensor(P.f))
+        ps.append(torch.zeros(P.N, dtype=torch.float64, device="cuda"))
+        q = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        st = prob.solve(fs[-1], q, P.tol)
+        assert st.status == 0
+        singles.append(q.cpu().numpy())
+    stats = mscg.solve_batch(probs, fs, ps, [P.tol for P, _ in jobs])
+    torch.cuda.synchronize()
+    for st, p, s in zip(stats, ps, singles):
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert np.array_equal(p.cpu().numpy(), s)

@@ -62,3 +62,30 @@ def test_create_rejects_small_workspace_before_any_launch():
     rc = L.mscg_create_problem(ctypes.byref(g), ctypes.byref(o), ctypes.c_void_p(256), 16, None, ctypes.byref(h))
     assert rc == mscg.E_NOMEM
     assert "workspace" in mscg.last_error()
+
+
+def test_default_cycle_and_scale():
+    L = mscg.load_library()
+    o = mscg._Options()
+    L.mscg_default_options(ctypes.byref(o))
+    assert (o.cycle, o.splitting) == (mscg.CYCLE_RECURSIVE, mscg.SPLIT_SGS)
+    assert o.frac_scale == 0.0
+
+
+def test_cycle_and_fractional_scale_arguments():
+    # a 50^2 grid cannot be divided by 4, but the rounded factor plans it: 50 -> 13 (-> 3 < 8 stops)
+    g = mscg.Grid(dim=2, n=(50, 50))
+    assert mscg.footprint_bytes(g, mscg.Options(frac_scale=4.0)) > 0
+    # 1001^2 with the factor of Table 1 gives levels 1001, 252, 63, 16 (and 4 with min side 4)
+    big = mscg.footprint_bytes(mscg.Grid(dim=2, n=(1001, 1001)), mscg.Options(frac_scale=3.98, min_coarse_side=4))
+    assert 1001 * 1001 * 8 * 7 < big < 1001 * 1001 * 8 * 12
+    with pytest.raises(mscg.MscgError, match="frac_scale"):
+        mscg.footprint_bytes(g, mscg.Options(frac_scale=0.5))
+    with pytest.raises(mscg.MscgError, match="frac_scale"):
+        mscg.footprint_bytes(g, mscg.Options(frac_scale=17.0))
+    with pytest.raises(mscg.MscgError, match="semi_coarsen"):
+        mscg.footprint_bytes(g, mscg.Options(frac_scale=3.0, semi_coarsen=1))
+    with pytest.raises(mscg.MscgError, match="cycle"):
+        mscg.footprint_bytes(mscg.Grid(dim=2, n=(32, 32)), mscg.Options(cycle=3))
+    for cyc in (mscg.CYCLE_RECURSIVE, mscg.CYCLE_MGCG, mscg.CYCLE_POLY):
+        assert mscg.footprint_bytes(mscg.Grid(dim=2, n=(32, 32)), mscg.Options(cycle=cyc)) > 0
