@@ -25,7 +25,7 @@ PEAK_FP64_CU_TFLOPS = 78.6 / 256  # MI355X FP64 vector peak per CU (256 CUs)
 # over `bench.py --kernels-only 10`; FETCH_SIZE scaled by 1.9993 (what the counter reads for a plain
 # copy of known size), WRITE_SIZE by 1.0.  Taken for the kernels as they stand; a kernel change
 # invalidates its figure.
-PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 361258, "smooth_pre": 36879673, "smooth_post": 47134059,
+PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 417049, "smooth_pre": 36879673, "smooth_post": 47134059,
                           "spmv": 33818263}
 
 WORKLOADS = {

@@ -518,8 +518,8 @@ int apply_prec(mscg_problem* P, int k, void** out, const int* gate, int* nfused 
 // On the deepest host-driven level the iteration holds no host decision (the
 // coarse correction runs entirely on the device), so iterations are queued
 // ahead in batches, gated on the level's converged flag, and the host waits
-// once per batch: as many as the level's last call needed plus one, then two
-// at a time.  Iterations queued past convergence return at once.
+// once per batch: as many as the level's last call needed, then two at a
+// time.  Iterations queued past convergence return at once.
 template <typename R>
 int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p2, R* q, int max_iter) {
   LevelH& H = P->lev[k];
@@ -532,7 +532,7 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p
   int rc = MSCG_OK;
   while (queued < max_iter) {
     int batch = 1;
-    if (ahead) batch = std::max(1, std::min(queued == 0 ? P->spec_hint[k] + 1 : 2, max_iter - queued));
+    if (ahead) batch = std::max(1, std::min(queued == 0 ? P->spec_hint[k] : 2, max_iter - queued));
     for (int b = 0; b < batch; ++b, ++queued) {
       void* zres = nullptr;
       int nfused = 0;
