@@ -441,7 +441,9 @@ R* precond_host(mscg_problem* P, int k, const Lv<R>& L, const R* r, R* z, R* w, 
   }
   *rc = coarse_correction<R>(P, k, xs, rs, zs, ps, qs, gate);
   if (*rc) return nullptr;
-  if (tiled) {
+  // the tiled post-smoother's fused prolongation assumes integer factors; the
+  // tiled residual + restriction above falls back by itself
+  if (tiled && !X.frac) {
     // the post-smoother also leaves the CG's r . z in per-tile partials
     double* fpart = nullptr;
     if (nfused && P->fuse_dot && !P->o.flexible) {
@@ -772,8 +774,7 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   P->ready = false;
   {
     const char* e = getenv("MSCG_UNTILED");
-    // the tiled kernels' transfers assume integer factors
-    P->tiled = !(e && e[0] == '1') && P->o.frac_scale == 0.0;
+    P->tiled = !(e && e[0] == '1');
     const char* fd = getenv("MSCG_FUSED_DOT");
     P->fuse_dot = !(fd && fd[0] == '0');
     const char* ff = getenv("MSCG_FUSED_FINISH");
