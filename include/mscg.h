@@ -193,15 +193,17 @@ int mscg_apply_operator(mscg_problem *prob, int level, const double *x, double *
 int mscg_apply_smoother(mscg_problem *prob, int level, const double *r, double *x, int steps);
 
 /* g_coarse = R (r_fine - A x_fine) between level and level + 1 (R = E^T;
- * x_fine may be NULL for zero). */
+ * x_fine may be NULL for zero).  MSCG_E_ARG on hierarchies with a
+ * non-integer frac_scale (their restriction works on a stored residual). */
 int mscg_restrict_residual(mscg_problem *prob, int level, const double *r_fine, const double *x_fine, double *g_coarse);
 
-/* x_fine += E y_coarse between level and level + 1. */
+/* x_fine += E y_coarse between level and level + 1 (any factor). */
 int mscg_prolong_add(mscg_problem *prob, int level, const double *y_coarse, double *x_fine);
 
 /* z = M_0^-1 r, the finest-level preconditioner of eq. 2.10 with inner
  * levels stopped at |r_k|^2 / N_k < f^k eps2 (eps2 = 0 runs them to
- * max_inner_iters).  FP64 problems only. */
+ * max_inner_iters); with MSCG_CYCLE_MGCG eq. 2.9, with MSCG_CYCLE_POLY the
+ * polynomial preconditioner (eps2 unused).  FP64 problems only. */
 int mscg_apply_preconditioner(mscg_problem *prob, const double *r, double *z, double eps2);
 
 /* ---- Measurement ---- */
@@ -221,7 +223,9 @@ enum {
  * reports its average duration (HIP events) and its algorithmic bytes per
  * launch: every operand array read once and written once.  Operates on the
  * problem's own work vectors (their contents are overwritten).  Needs
- * mscg_set_permeability; run a solve first so the vectors hold finite values. */
+ * mscg_set_permeability; run a solve first so the vectors hold finite values.
+ * MSCG_KERNEL_RESTRICT and MSCG_KERNEL_SMOOTH_POST are not available on
+ * hierarchies with a non-integer frac_scale (MSCG_E_ARG). */
 int mscg_time_kernel(mscg_problem *prob, int kernel, int level, int reps, double *avg_us, double *alg_bytes);
 
 /* Launch timing of the one-workgroup solver of the last inner level (the
