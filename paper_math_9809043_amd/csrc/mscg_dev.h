@@ -324,6 +324,66 @@ __device__ __forceinline__ void restrict_stored_range(const Lv<R>& F, const Xfer
   }
 }
 
+// The same transfers for factors that need not be integers (X.frac): x_fine
+// += E y over fine cells [t0, n) step nt, and g = E^T res over coarse cells
+// [t0, nc) step nt, gathering the fine cells whose extension touches each
+// coarse cell.  Weights from ext_weights_frac.
+template <typename R>
+__device__ __forceinline__ void prolong_frac_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ y,
+                                                   R* __restrict__ x, int t0, int nt) {
+  for (int c = t0; c < F.n; c += nt) {
+    int i, j, k;
+    cell_ijk(c, F.nx, F.ny, i, j, k);
+    int I[2], J[2], K[2];
+    R wi[2], wj[2], wk[2];
+    ext_weights_frac<R>(i, F.nx, X.cnx, X.interp, I[0], wi[0], I[1], wi[1]);
+    ext_weights_frac<R>(j, F.ny, X.cny, X.interp, J[0], wj[0], J[1], wj[1]);
+    ext_weights_frac<R>(k, F.nz, X.cnz, X.interp, K[0], wk[0], K[1], wk[1]);
+    R v = R(0);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 2; ++e) {
+          const R w = wk[a] * wj[b] * wi[e];
+          if (w != R(0)) v += w * y[I[e] + X.cnx * (J[b] + X.cny * K[a])];
+        }
+    x[c] += v;
+  }
+}
+
+__device__ __forceinline__ void frac_support(int I, int nf, int nc, int& lo, int& hi) {
+  if (nf == nc) { lo = hi = I; return; }
+  const double f = (double)nf / nc;
+  lo = max((int)floor((I - 1) * f) - 1, 0);
+  hi = min((int)ceil((I + 2) * f) + 1, nf - 1);
+}
+
+template <typename R>
+__device__ __forceinline__ void restrict_frac_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ res,
+                                                    R* __restrict__ g, int t0, int nt) {
+  const int nc = X.cnx * X.cny * X.cnz;
+  for (int c = t0; c < nc; c += nt) {
+    const int I = c % X.cnx, J = (c / X.cnx) % X.cny, K = c / (X.cnx * X.cny);
+    int ilo, ihi, jlo, jhi, klo, khi;
+    frac_support(I, F.nx, X.cnx, ilo, ihi);
+    frac_support(J, F.ny, X.cny, jlo, jhi);
+    frac_support(K, F.nz, X.cnz, klo, khi);
+    R acc = R(0);
+    for (int k = klo; k <= khi; ++k) {
+      const R wk = ext_weight_of_frac<R>(k, K, F.nz, X.cnz, X.interp);
+      if (wk == R(0)) continue;
+      for (int j = jlo; j <= jhi; ++j) {
+        const R wj = ext_weight_of_frac<R>(j, J, F.ny, X.cny, X.interp);
+        if (wj == R(0)) continue;
+        for (int i = ilo; i <= ihi; ++i) {
+          const R wi = ext_weight_of_frac<R>(i, I, F.nx, X.cnx, X.interp);
+          if (wi != R(0)) acc += wk * wj * wi * res[i + F.nx * (j + F.ny * k)];
+        }
+      }
+    }
+    g[c] = acc;
+  }
+}
+
 // x_fine += E y_coarse for fine cells [t0, n) step nt.
 template <typename R>
 __device__ __forceinline__ void prolong_range(const Lv<R>& F, const Xfer& X, const R* __restrict__ y,

@@ -753,9 +753,9 @@ int mscg_create_problem(const mscg_grid* grid, const mscg_options* opt, void* wo
   if (rc) { mscg_destroy_problem(P); return rc; }
   const int sn = small_n();
   P->ks = P->nlev;  // no small level
-  // the one-workgroup solvers smooth by red-black SGS only, run an inner PCG
-  // and use integer factors
-  if (P->o.splitting == MSCG_SPLIT_SGS && P->o.cycle == MSCG_CYCLE_RECURSIVE && P->o.frac_scale == 0.0)
+  // the one-workgroup solvers smooth by red-black SGS only and run an inner
+  // PCG (with non-integer factors the generic one takes the level)
+  if (P->o.splitting == MSCG_SPLIT_SGS && P->o.cycle == MSCG_CYCLE_RECURSIVE)
     for (int l = 1; l < P->nlev - 1; ++l)
       if (P->lev[l].n <= sn) { P->ks = l; break; }
   for (int l = 0; l < P->nlev; ++l) {

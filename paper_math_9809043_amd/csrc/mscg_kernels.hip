@@ -211,23 +211,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_prolong_frac(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x,
                                                           const int* __restrict__ gate) {
   if (gate && *gate) return;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < F.n; c += gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_ijk(c, F.nx, F.ny, i, j, k);
-    int I[2], J[2], K[2];
-    R wi[2], wj[2], wk[2];
-    ext_weights_frac<R>(i, F.nx, X.cnx, X.interp, I[0], wi[0], I[1], wi[1]);
-    ext_weights_frac<R>(j, F.ny, X.cny, X.interp, J[0], wj[0], J[1], wj[1]);
-    ext_weights_frac<R>(k, F.nz, X.cnz, X.interp, K[0], wk[0], K[1], wk[1]);
-    R v = R(0);
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
-        for (int e = 0; e < 2; ++e) {
-          const R w = wk[a] * wj[b] * wi[e];
-          if (w != R(0)) v += w * y[I[e] + X.cnx * (J[b] + X.cny * K[a])];
-        }
-    x[c] += v;
-  }
+  prolong_frac_range(F, X, y, x, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // g = E^T res for factors that need not be integers: one thread per coarse
@@ -236,34 +220,7 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_restrict_frac(Lv<R> F, Xfer X, const R* __restrict__ res, R* __restrict__ g,
                                                            const int* __restrict__ gate) {
   if (gate && *gate) return;
-  const int nc = X.cnx * X.cny * X.cnz;
-  auto range = [](int I, int nf, int ncs, int& lo, int& hi) {
-    if (nf == ncs) { lo = hi = I; return; }
-    const double f = (double)nf / ncs;
-    lo = max((int)floor((I - 1) * f) - 1, 0);
-    hi = min((int)ceil((I + 2) * f) + 1, nf - 1);
-  };
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-    const int I = c % X.cnx, J = (c / X.cnx) % X.cny, K = c / (X.cnx * X.cny);
-    int ilo, ihi, jlo, jhi, klo, khi;
-    range(I, F.nx, X.cnx, ilo, ihi);
-    range(J, F.ny, X.cny, jlo, jhi);
-    range(K, F.nz, X.cnz, klo, khi);
-    R acc = R(0);
-    for (int k = klo; k <= khi; ++k) {
-      const R wk = ext_weight_of_frac<R>(k, K, F.nz, X.cnz, X.interp);
-      if (wk == R(0)) continue;
-      for (int j = jlo; j <= jhi; ++j) {
-        const R wj = ext_weight_of_frac<R>(j, J, F.ny, X.cny, X.interp);
-        if (wj == R(0)) continue;
-        for (int i = ilo; i <= ihi; ++i) {
-          const R wi = ext_weight_of_frac<R>(i, I, F.nx, X.cnx, X.interp);
-          if (wi != R(0)) acc += wk * wj * wi * res[i + F.nx * (j + F.ny * k)];
-        }
-      }
-    }
-    g[c] = acc;
-  }
+  restrict_frac_range(F, X, res, g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
@@ -1169,7 +1126,8 @@ __global__ void __launch_bounds__(1024, 1) k_small_pcg(SmallArgs<R> args) {
       S.q[c] = S.r[c] - (d * S.z[c] - o);
     }
     __syncthreads();
-    restrict_stored_range(S.L, S.X, (const R*)S.q, lv[k + 1].r, tid, nt);
+    if (S.X.frac) restrict_frac_range(S.L, S.X, (const R*)S.q, lv[k + 1].r, tid, nt);
+    else restrict_stored_range(S.L, S.X, (const R*)S.q, lv[k + 1].r, tid, nt);
     __syncthreads();
   };
   // y = A^-1 g on the coarsest level: the columns of A^-1 are split into
@@ -1202,7 +1160,8 @@ __global__ void __launch_bounds__(1024, 1) k_small_pcg(SmallArgs<R> args) {
   // post-smoothing of level k and one CG step; returns true when level k is done
   auto post_step = [&](int k) -> bool {
     SmallLevel<R>& S = lv[k];
-    prolong_range(S.L, S.X, lv[k + 1].x, S.z, tid, nt);
+    if (S.X.frac) prolong_frac_range(S.L, S.X, lv[k + 1].x, S.z, tid, nt);
+    else prolong_range(S.L, S.X, lv[k + 1].x, S.z, tid, nt);
     __syncthreads();
     for (int h = 0; h <= 2 * a.m; ++h) {
       gs_half_range(S.L, S.r, S.z, h & 1, false, tid, nt);

@@ -309,6 +309,9 @@ hipError_t launch_small_reg(const SmallDesc<R>& d, hipStream_t s) {
   // colour-split kernel (both precisions); the rest to the cell-strided kernel
   // below.
   const int ks = d.ks, L = d.nlev - 1;
+  // these kernels bake in integer factors; the generic one takes the rest
+  for (int l = ks; l < L; ++l)
+    if (d.X[l].frac) return hipErrorNotSupported;
   if (ks + 1 != L) return hipErrorNotSupported;
   const Lv<R>& V = d.L[ks];
   if (V.n > kOwn * kThreads) return hipErrorNotSupported;
