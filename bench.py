@@ -367,8 +367,18 @@ def main():
             print(f"[bench] smooth1001 factor 3.98 {label}: {wallf:.2f} ms/step (outer {stf.outer_iters}, levels "
                   f"{stf.level_iters})", flush=True)
         extra["smooth1001_frac3.98"] = dict({"workload": "2-D, 1001x1001, log10 k ~ U[-3,3] then 3x3 box mean, tol "
-                                             "1e-10; non-integer factor 3.98 (levels 1001, 252, 63, 16, 4), "
-                                             "host-driven grid-wide kernels on every level"}, **res)
+                                             "1e-10; non-integer factor 3.98 (levels 1001, 252, 63, 16, 4)"}, **res)
+        # the paper's scale-factor study (Section 4): the same problem coarsened by other factors
+        sweep = []
+        for fs in (2.5, 3.0, 3.5, 3.98, 5.0):
+            _, sts, walls, _, _ = run_gpu(Pf, {"frac_scale": fs, "min_coarse_side": 4}, 2, 1)
+            sweep.append({"factor": fs, "ms_per_step": round(walls, 3), "ns_per_unknown": round(walls * 1e6 / Pf.N, 2),
+                          "outer_iters": sts.outer_iters, "level_n": [d[0] for d in sts.level_n],
+                          "level_iters": sts.level_iters, "status": sts.status})
+            print(f"[bench] smooth1001 factor {fs}: {walls:.2f} ms/step, levels {[d[0] for d in sts.level_n]}, "
+                  f"iterations {sts.level_iters}", flush=True)
+        extra["smooth1001_scale_factor_sweep"] = {"workload": "the same 1001^2 problem, FP64, factor per level",
+                                                  "rows": sweep}
 
     scaling = None
     if not args.no_scaling:
