@@ -647,3 +647,32 @@ def test_batch_matches_single_for_every_cycle_and_fractional_plans():
     for st, p, s in zip(stats, ps, singles):
         assert st.status == 0 and st.rel_residual_true <= 1e-10
         assert np.array_equal(p.cpu().numpy(), s)
+
+
+SCALE_CASES = [
+    ("smooth96_s2", lambda: synth.smoothed_lognormal_2d(3, 96, lo=-3, hi=3), 2),
+    ("smooth128_s2", lambda: synth.smoothed_lognormal_2d(3, 128, lo=-3, hi=3), 2),
+    ("smooth216_s3", lambda: synth.smoothed_lognormal_2d(3, 216, lo=-3, hi=3), 3),
+    ("smooth512_s8", lambda: synth.smoothed_lognormal_2d(3, 512, lo=-3, hi=3), 8),
+]
+
+
+@pytest.mark.parametrize("name,make,sc", SCALE_CASES, ids=[c[0] for c in SCALE_CASES])
+def test_integer_scale_factors_parity(name, make, sc):
+    """Integer factors other than 4 (with m = s smoothing steps, Section 3):
+    grid-wide smoothing, the generic transfer footprints and the one-workgroup
+    solvers' factor checks, FP64 and mixed, against the oracle."""
+    from paper_math_9809043_amd import mscg
+    case(f"integer scale {name}")
+    P = make()
+    ref = oracle.solve(P, scale=sc)
+    assert ref.status == 0 and ref.nlev >= 3
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec, scale=sc)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: levels {st.level_n} outer {st.outer_iters} (oracle {ref.outer_iters}) iters "
+              f"{st.level_iters} (oracle {ref.level_iters}) res {st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert [tuple(d) for d in st.level_n] == [tuple(d) for d in ref.level_n]
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
