@@ -676,3 +676,31 @@ def test_integer_scale_factors_parity(name, make, sc):
         assert st.status == 0 and st.rel_residual_true <= 1e-10
         assert err <= 1e-8
         assert abs(st.outer_iters - ref.outer_iters) <= 2
+
+
+KNOB_CASES = [
+    ("smooth256_m2", {"smooth_steps": 2}, {"m": 2}),
+    ("smooth256_m6", {"smooth_steps": 6}, {"m": 6}),
+    ("smooth256_f0.3", {"level_factor": 0.3}, {"flvl": 0.3}),
+    ("smooth256_f0.02", {"level_factor": 0.02}, {"flvl": 0.02}),
+]
+
+
+@pytest.mark.parametrize("name,gopt,oopt", KNOB_CASES, ids=[c[0] for c in KNOB_CASES])
+def test_smoothing_steps_and_level_factor_parity(name, gopt, oopt):
+    """The other knobs of the method (Section 3): m smoothing steps away from
+    the tiled smoother's m = 4, and the level factor f of the per-level
+    criterion, FP64 and mixed, against the oracle."""
+    from paper_math_9809043_amd import mscg
+    case(f"knobs {name}")
+    P = synth.smoothed_lognormal_2d(1, 256, lo=-3, hi=3)
+    ref = oracle.solve(P, **oopt)
+    assert ref.status == 0
+    for prec in (mscg.FP64, mscg.MIXED):
+        st, x, _ = gpu_solve(P, precision=prec, **gopt)
+        err = np.linalg.norm(x - ref.p) / np.linalg.norm(ref.p)
+        print(f"  precision {prec}: outer {st.outer_iters} (oracle {ref.outer_iters}) iters {st.level_iters} "
+              f"(oracle {ref.level_iters}) res {st.rel_residual_true:.2e} err {err:.2e}", flush=True)
+        assert st.status == 0 and st.rel_residual_true <= 1e-10
+        assert err <= 1e-8
+        assert abs(st.outer_iters - ref.outer_iters) <= 2
