@@ -25,7 +25,7 @@ PEAK_FP64_CU_TFLOPS = 78.6 / 256  # MI355X FP64 vector peak per CU (256 CUs)
 # over `bench.py --kernels-only 10`; FETCH_SIZE scaled by 1.9993 (what the counter reads for a plain
 # copy of known size), WRITE_SIZE by 1.0.  Taken for the kernels as they stand; a kernel change
 # invalidates its figure.
-PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 417049, "smooth_pre": 36879673, "smooth_post": 47134059,
+PMC_TRAFFIC_SMOOTH1024 = {"small_2x2": 417049, "smooth_pre": 36879673, "smooth_post": 64656465,
                           "spmv": 33818263}
 
 WORKLOADS = {
@@ -260,8 +260,8 @@ def main():
     kernels = [(mscg.KERNEL_SPMV, "k_spmv_dot<double> (finest level)", "spmv")]
     if P.dim == 2:
         kernels = [(mscg.KERNEL_SMOOTH_PRE, "k_smooth_tile<double, pre> (finest level, 9 half sweeps)", "smooth_pre"),
-                   (mscg.KERNEL_SMOOTH_POST, "k_smooth_tile<double, post> (finest level, prolongation + 9 half "
-                                             "sweeps)", "smooth_post")] + kernels
+                   (mscg.KERNEL_SMOOTH_POST, "k_prolong_2d<double> + k_smooth_tile<double, post> (finest level, "
+                                             "prolongation, then 9 half sweeps)", "smooth_post")] + kernels
     for kid, name, key in kernels:
         us, nbytes = prob.time_kernel(kid, 0, reps=50)
         gbs = nbytes / (us * 1e-6) / 1e9

@@ -671,6 +671,31 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Lv<R> F, Xfer X, const R* __
   prolong_range(F, X, y, x, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
+// The same on a 2-D level, one workgroup per stretch of a fine row: the row's
+// weights are the workgroup's, the column's the thread's, with no per-cell
+// index division.  Same products in the same order as prolong_range (the z
+// weight is 1 in 2-D), so the result is the same bit for bit.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_prolong_2d(Lv<R> F, Xfer X, const R* __restrict__ y, R* __restrict__ x,
+                                                        const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= F.nx) return;
+  int I[2], J[2];
+  R wi[2], wj[2];
+  ext_weights<R>(i, X.sx, X.cnx, X.interp, I[0], wi[0], I[1], wi[1]);
+  ext_weights<R>(j, X.sy, X.cny, X.interp, J[0], wj[0], J[1], wj[1]);
+  R v = R(0);
+  for (int b = 0; b < 2; ++b) {
+    if (wj[b] == R(0)) continue;
+    for (int e = 0; e < 2; ++e) {
+      if (wi[e] == R(0)) continue;
+      v += (R(1) * wj[b] * wi[e]) * y[I[e] + X.cnx * J[b]];
+    }
+  }
+  x[i + F.nx * j] += v;
+}
+
 // y = A^-1 g on the coarsest level (dense FP64 inverse; g, y in R).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restrict__ Ainv, const R* __restrict__ g,
@@ -1441,7 +1466,10 @@ hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipSt
   if (X.frac)
     hipLaunchKernelGGL(k_prolong_frac<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
   else
-    hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
+    if (F.nz == 1 && X.cnz == 1 && !F.tz && F.ny <= 65535)
+      hipLaunchKernelGGL(k_prolong_2d<R>, dim3((F.nx + kBlock - 1) / kBlock, F.ny), dim3(kBlock), 0, s, F, X, y, x, gate);
+    else
+      hipLaunchKernelGGL(k_prolong<R>, dim3(grid_for(F.n, 1 << 20)), dim3(kBlock), 0, s, F, X, y, x, gate);
   return hipGetLastError();
 }
 

@@ -44,7 +44,9 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   bx = t - by * gx;
 }
 
-template <typename R, bool POST, int TW, int TH, int BX, int BY>
+// POST: continue from zin (post-smoothing); PROL: apply the prolongation
+// zin + E y while loading (else zin already holds it).
+template <typename R, bool POST, int TW, int TH, int BX, int BY, bool PROL = POST>
 __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4 : 1) k_smooth_tile(Lv<R> L, Xfer X, const R* __restrict__ r,
                                                          const R* __restrict__ zin, const R* __restrict__ y,
                                                          R* __restrict__ zout, const int* __restrict__ gate,
@@ -69,6 +71,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
   // limit, stages the coarse patch first (gate, patch, then the coefficients:
   // three round trips, fewer live registers).
   constexpr bool kEarly = !POST || TW * TH <= 196 || BY >= 16;
+  static_assert(kEarly || PROL == POST, "the staged-patch path always applies the prolongation");
   R cw[NR][2], ce[NR][2], cs[NR][2], cn[NR][2], dg[NR][2], rr[NR][2];
   if constexpr (kEarly) {
     // Region cell (li, lj) has colour (rx0 + li + ry0 + lj) & 1 and index li >> 1
@@ -98,14 +101,14 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
     // post-smoothing: the coarse values the region's prolongation reads are
     // staged in LDS when the patch fits (factors >= 2 per axis)
     constexpr int kPW = MW / 2 + 2, kPH = MH / 2 + 2;
-    constexpr int kYPer = POST ? (kPW * kPH + BX * BY - 1) / (BX * BY) : 1;
-    __shared__ R ys[POST ? kPW * kPH : 1];
+    constexpr int kYPer = PROL ? (kPW * kPH + BX * BY - 1) / (BX * BY) : 1;
+    __shared__ R ys[PROL ? kPW * kPH : 1];
     int xI0[2], xI1[2];
     R xw0[2], xw1[2];
     int pI = 0, pJ = 0, PW = 0, PH = 0;
     bool staged = false;
     R yv_[kYPer];
-    if (POST) {
+    if (PROL) {
       int a0, a1, b0, b1;
       R u0, u1;
       ext_weights<R>(rx0, X.sx, X.cnx, X.interp, a0, u0, a1, u1);
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
     }
     asm volatile("" ::"v"(gv));  // the gate's wait comes after every load is issued
     if (gv) return;
-    if (POST) {
+    if (PROL) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) ext_weights<R>(rx0 + 2 * k + q, X.sx, X.cnx, X.interp, xI0[q], xw0[q], xI1[q], xw1[q]);
       if (staged) {
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
       const int j = ry0 + lj;
       int J0 = 0, J1 = 0;
       R wj0 = R(0), wj1 = R(0);
-      if (POST && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
+      if (PROL && lj < RH) ext_weights<R>(j, X.sy, X.cny, X.interp, J0, wj0, J1, wj1);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int q = (rx0 + ry0 + lj + c) & 1;
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
           if (!(i < nx - 1 && li < RW - 1)) ce[b][c] = R(0);
           if (!(j > 0 && lj > 0)) cs[b][c] = R(0);
           if (!(j < ny - 1 && lj < RH - 1)) cn[b][c] = R(0);
-          if (POST) {
+          if (PROL) {
             // same products, in the same order, as the grid-wide prolongation
             R v = R(0);
             if (wj0 != R(0)) {
@@ -171,6 +174,8 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
               if (xw1[q] != R(0)) v += (R(1) * wj1 * xw1[q]) * yv(xI1[q], J1);
             }
             zc[c][lj][k] = zp[b][c] + v;
+          } else if (POST) {
+            zc[c][lj][k] = zp[b][c];
           }
         }
       }
@@ -323,11 +328,18 @@ __global__ void __launch_bounds__(BX* BY, (BX * BY == 256 && sizeof(R) == 8) ? 4
   }
 }
 
-template <typename R, int TW, int TH, int BX, int BY>
+// FUSED = false: the post-smoother continues from zin, which already holds
+// the prolongation
+template <typename R, int TW, int TH, int BX, int BY, bool FUSED = true>
 hipError_t launch_tiles(const Lv<R>& L, const Xfer* X, const R* r, const R* zin, const R* y, R* zout, hipStream_t s,
                         const int* gate, double* part) {
   const dim3 grid((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
   const dim3 block(BX * BY);
+  if constexpr (!FUSED) {
+    hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY, false>), grid, block, 0, s, L, *X, r, zin, y, zout,
+                       gate, part);
+    return hipGetLastError();
+  }
   if (X)
     hipLaunchKernelGGL((k_smooth_tile<R, true, TW, TH, BX, BY>), grid, block, 0, s, L, *X, r, zin, y, zout, gate,
                        part);
@@ -492,8 +504,15 @@ hipError_t launch_smooth_tile(const Lv<R>& L, const Xfer* X, const R* r, const R
     case 0: return launch_tiles<R, 64, 32, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
     case 1: return launch_tiles<R, 110, 38, 64, 8>(L, X, r, zin, y, zout, s, gate, part);
     case 2:  // one region row per thread for the pre-smoother, two for the post-smoother
-      return X ? launch_tiles<R, 46, 14, 32, 16>(L, X, r, zin, y, zout, s, gate, part)
-               : launch_tiles<R, 46, 14, 32, 32>(L, X, r, zin, y, zout, s, gate, part);
+      if (X) {
+        // the prolongation as a grid-wide pass in place on zin, then the
+        // sweeps from zin: fused into the tiles it held more registers (fewer
+        // waves) than it saved in traffic
+        const hipError_t e = launch_prolong<R>(L, *X, y, const_cast<R*>(zin), s, gate);
+        if (e != hipSuccess) return e;
+        return launch_tiles<R, 46, 14, 32, 16, false>(L, X, r, zin, y, zout, s, gate, part);
+      }
+      return launch_tiles<R, 46, 14, 32, 32>(L, X, r, zin, y, zout, s, gate, part);
     default: return launch_tiles<R, 14, 14, 16, 32>(L, X, r, zin, y, zout, s, gate, part);
   }
 }
