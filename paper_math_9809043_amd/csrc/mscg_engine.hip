@@ -526,7 +526,11 @@ template <typename R>
 int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p2, R* q, int max_iter) {
   LevelH& H = P->lev[k];
   const int nb = reduce_blocks(L.n);
-  const bool ahead = P->queue_ahead && k > 0 && (k + 1 == P->nlev - 1 || k + 1 >= P->ks);
+  // With Tatebe's or the polynomial preconditioner in FP64 a finest-level
+  // iteration holds no host decision either (no inner PCG), so it is queued
+  // the same way.
+  const bool outer_device = k == 0 && !mixed(P) && !P->o.flexible && P->o.cycle != MSCG_CYCLE_RECURSIVE;
+  const bool ahead = P->queue_ahead && ((k > 0 && (k + 1 == P->nlev - 1 || k + 1 >= P->ks)) || outer_device);
   const int* gate = ahead ? &H.sc->converged : nullptr;
   R* pc = p;
   R* pn = p2;
@@ -579,7 +583,13 @@ int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p
   P->iters[k] += P->hsc->started;
   if (ahead) {
     P->spec_hint[k] = P->hsc->started;
-    if (k + 1 == P->nlev - 1) P->calls[k + 1] += P->hsc->started;
+    if (outer_device) {
+      // every coarser level is visited once per finest-level iteration (eq. 2.9)
+      if (P->o.cycle == MSCG_CYCLE_MGCG)
+        for (int l = 1; l < P->nlev; ++l) P->calls[l] += P->hsc->started;
+    } else if (k + 1 == P->nlev - 1) {
+      P->calls[k + 1] += P->hsc->started;
+    }
   }
   return MSCG_OK;
 }
