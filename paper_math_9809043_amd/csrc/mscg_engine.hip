@@ -496,7 +496,7 @@ int apply_prec(mscg_problem* P, int k, void** out, const int* gate, int* nfused 
     LevelH& L0 = P->lev[0];
     HIP_TRY(launch_scale_to_f32(L0.r, L0.r32, L0.n, L0.sc, P->stream));
     float* z32 =
-        precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc, nullptr, nullptr);
+        precond_host<float>(P, 0, lv32(P, 0), L0.r32, L0.z32, L0.w32, xs, rs, zs, ps, qs, &rc, gate, nullptr);
     if (rc) return rc;
     HIP_TRY(launch_scale_to_f64(z32, L0.z, L0.n, L0.sc, P->stream));
     *out = L0.z;
@@ -526,10 +526,12 @@ template <typename R>
 int cg_loop(mscg_problem* P, int k, const Lv<R>& L, R* x, R* r, R* z, R* p, R* p2, R* q, int max_iter) {
   LevelH& H = P->lev[k];
   const int nb = reduce_blocks(L.n);
-  // With Tatebe's or the polynomial preconditioner in FP64 a finest-level
-  // iteration holds no host decision either (no inner PCG), so it is queued
-  // the same way.
-  const bool outer_device = k == 0 && !mixed(P) && !P->o.flexible && P->o.cycle != MSCG_CYCLE_RECURSIVE;
+  // With Tatebe's or the polynomial preconditioner a finest-level iteration
+  // holds no host decision either (no inner PCG; the mixed-precision
+  // rescaling of inner tolerances has nothing to act on), so it is queued the
+  // same way.  The FP64 <-> FP32 conversions around the mixed preconditioner
+  // are not gated; past convergence they only rewrite work vectors.
+  const bool outer_device = k == 0 && !P->o.flexible && P->o.cycle != MSCG_CYCLE_RECURSIVE;
   const bool ahead = P->queue_ahead && ((k > 0 && (k + 1 == P->nlev - 1 || k + 1 >= P->ks)) || outer_device);
   const int* gate = ahead ? &H.sc->converged : nullptr;
   R* pc = p;
