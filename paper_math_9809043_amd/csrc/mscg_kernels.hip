@@ -700,12 +700,18 @@ __global__ void __launch_bounds__(kBlock) k_prolong_2d(Lv<R> F, Xfer X, const R*
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restrict__ Ainv, const R* __restrict__ g,
                                                           R* __restrict__ y, int n, const int* __restrict__ gate) {
+  // y = A^-1 g with one wave per output: A^-1 is symmetric, so output i is
+  // the dot product of the stored row i (contiguous) with g.  Lane l sums the
+  // columns l, l + 64, ..., then a fixed-order wave sum: the same bits on
+  // every run.  A whole wave leaves together when it has no row.
   if (gate && *gate) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x % kWave, i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   if (i >= n) return;
+  const double* row = Ainv + (long long)i * n;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += Ainv[(long long)j * n + i] * (double)g[j];
-  y[i] = (R)s;
+  for (int j = lane; j < n; j += kWave) s += row[j] * (double)g[j];
+  s = wave_total(s);
+  if (lane == 0) y[i] = (R)s;
 }
 
 // Keeps a loaded value live at this point, so that a load whose result is only
@@ -1475,7 +1481,9 @@ hipError_t launch_prolong(const Lv<R>& F, const Xfer& X, const R* y, R* x, hipSt
 
 template <typename R>
 hipError_t launch_coarse_solve(const double* Ainv, const R* g, R* y, int n, hipStream_t s, const int* gate) {
-  hipLaunchKernelGGL(k_coarse_solve<R>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Ainv, g, y, n, gate);
+  constexpr int kRowsPerBlock = kBlock / kWave;
+  hipLaunchKernelGGL(k_coarse_solve<R>, dim3((n + kRowsPerBlock - 1) / kRowsPerBlock), dim3(kBlock), 0, s, Ainv, g, y,
+                     n, gate);
   return hipGetLastError();
 }
 
